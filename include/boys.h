@@ -1,0 +1,172 @@
+/*
+ * boys.h -- C-ABI of the MI355X (gfx950) Boys-function library libboys.so.
+ *
+ * Evaluates the Boys functions
+ *
+ *     F_k(x) = integral_0^1 t^(2k) exp(-x t^2) dt,   x >= 0, k = 0, 1, ...
+ *
+ * (Vikhamar-Sandberg and Repisky, "Efficient Boys function evaluation using
+ * minimax approximation", arXiv 2512.10059, Sec. I eq. 3) with the paper's
+ * method (Sec. II F, Algorithm 1): the axis is split into A = [0, x0),
+ * B = [x0, x1) and C = [x1, inf).  On A a rational minimax approximant
+ * r_{A,k} gives F_k and the downward recurrence the lower orders; on B the
+ * approximant r_B gives F_0 and the upward recurrence the higher orders; on C
+ * the asymptotic form sqrt(pi)/(2 sqrt x) and its upward recurrence are used.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller (for
+ *    example the storage of a torch tensor).  The library never frees it.
+ *  - Every call is asynchronous: it only enqueues kernels on `stream` (0 is
+ *    the null stream) and returns.  Results are ready when the stream has
+ *    executed them.
+ *  - Return value: BOYS_OK (0) or a negative status.  Argument errors
+ *    (BOYS_EINVAL) are detected on the host before anything is enqueued;
+ *    BOYS_EHIP reports a failed HIP runtime call (the HIP error is kept for
+ *    boys_last_hip_error()).  n == 0 is valid and enqueues nothing.
+ *  - Domain: x must be >= 0.  Negative x and NaN give NaN in every output
+ *    they feed; x = +inf gives 0.
+ *  - Accuracy: FP64 results are within 5e-14 absolute of the exact function
+ *    for 0 <= k <= 32 (the paper's appendix tables, eps_tol = 5e-14).
+ *  - The library keeps a small lazily created workspace per device (for the
+ *    batched entry point); boys_finalize() releases it.
+ *  - Calls are thread-safe with respect to each other except that two
+ *    concurrent boys_weighted_sum calls on one device share its workspace
+ *    and must be ordered by the caller (same stream, or synchronised).
+ */
+#ifndef BOYS_H
+#define BOYS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#if defined(__GNUC__)
+#define BOYS_API __attribute__((visibility("default")))
+#else
+#define BOYS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BOYS_OK = 0,
+    BOYS_EINVAL = -1,   /* bad argument: null pointer, size, order or stride */
+    BOYS_EHIP = -2,     /* a HIP runtime call failed */
+    BOYS_ENOTSUP = -3,  /* the current device is not supported (needs gfx950) */
+    BOYS_ENOMEM = -4    /* the workspace could not be allocated */
+};
+
+/* Highest order of the FP64 tables, and of the FP32 tables. */
+#define BOYS_F64_KMAX_LIMIT 32
+#define BOYS_F32_KMAX_LIMIT 16
+
+/* Text for a status code (static storage, never NULL). */
+BOYS_API const char *boys_strerror(int status);
+
+/* The hipError_t of the last failed HIP call made by this thread. */
+BOYS_API int boys_last_hip_error(void);
+
+/*
+ * F_0..F_kmax in FP64 (Algorithm 1, Sec. II F).
+ *
+ *   x      [n] FP64 arguments.
+ *   out    row-major n x ld_out FP64: out[i*ld_out + k] = F_k(x[i]) for
+ *          k = 0..kmax; columns kmax+1..ld_out-1 are left untouched.
+ *   kmax   0 <= kmax <= 32; r_{A,kmax} is the region-A approximant used.
+ *   ld_out row stride in elements, ld_out >= kmax + 1.
+ * Errors: BOYS_EINVAL for n < 0, kmax out of range, ld_out too small, a null
+ * pointer with n > 0, or x and out overlapping.
+ */
+BOYS_API int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, int64_t ld_out,
+                  hipStream_t stream);
+
+/*
+ * F_0..F_kmax in FP32 storage (mixed precision; the FP32 variant of
+ * Algorithm 1 with the library's own minimax coefficients, regions
+ * A' = [0, x0'), B' = [x0', x1'), C' = [x1', inf) for kmax <= 16).
+ * FP32 rational and downward recurrence on A'; FP64 rational and FP64 upward
+ * recurrence on B', where upward recurrence cancels; FP32 asymptote on C'.
+ * Results are within 1e-6 absolute of the exact function at the FP32 x.
+ *
+ *   x      [n] FP32 arguments.
+ *   out    row-major n x ld_out FP32, out[i*ld_out + k] = F_k(x[i]).
+ *   kmax   0 <= kmax <= 16.   ld_out >= kmax + 1.
+ * Errors as boys_eval_f64.
+ */
+BOYS_API int boys_eval_f32(const float *x, int64_t n, int kmax, float *out, int64_t ld_out,
+                  hipStream_t stream);
+
+/*
+ * Batched fused consumer: for every batch b and every argument i of it
+ *
+ *     out[i] = sum_{l=0..kmax_b} w[w_off[b] + l] * F_l(x[i]),
+ *
+ * the weighted sum the paper's benchmark accumulates inside the recurrence
+ * (Sec. III, Algorithm 2), here with one order and one weight vector per
+ * batch.  Batch b covers x[batch_off[b] .. batch_off[b] + batch_n[b]).
+ * One persistent kernel serves every batch; the library launches it through
+ * a cached hipGraph (rebuilt when an argument changes).
+ *
+ *   x, out     FP64 arrays indexed by batch_off; only batch elements of out
+ *              are written.
+ *   batch_off  [nbatch] int64 first argument of each batch (>= 0).
+ *   batch_n    [nbatch] int32 size of each batch (>= 0).
+ *   batch_kmax [nbatch] int32 order of each batch, 0..32.
+ *   w          FP64 weights; batch b uses w[w_off[b] .. w_off[b] + kmax_b].
+ *   w_off      [nbatch] int64.
+ *   nbatch     number of batches, 0 <= nbatch <= 2^24.
+ * The batch table lives in device memory and is not validated element by
+ * element: out-of-range orders are clamped to 0..32 in the kernel, and
+ * batches must not overlap in out.
+ * Errors: BOYS_EINVAL for a null pointer with nbatch > 0 or nbatch out of
+ * range; BOYS_ENOMEM if the workspace cannot grow.
+ */
+BOYS_API int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                      const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                      int32_t nbatch, double *out, hipStream_t stream);
+
+/*
+ * Times every tile/unroll configuration of the persistent kernel on these
+ * arguments (each run writes out), keeps the fastest for later
+ * boys_weighted_sum calls on this device, and reports it.  Synchronises
+ * `stream`.  best_config (may be NULL) receives the configuration index,
+ * best_ms (may be NULL) its time in milliseconds.
+ */
+BOYS_API int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                           const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                           int32_t nbatch, double *out, hipStream_t stream,
+                           int *best_config, float *best_ms);
+
+/* Number of persistent-kernel configurations, their description, and the one
+ * boys_weighted_sum uses now on the current device (set_config: -1 = auto). */
+BOYS_API int boys_weighted_sum_num_configs(void);
+BOYS_API const char *boys_weighted_sum_config_name(int config);
+BOYS_API int boys_weighted_sum_get_config(void);
+BOYS_API int boys_weighted_sum_set_config(int config);
+
+/*
+ * Backward pass of F_0..F_kmax with respect to x, from dF_k/dx = -F_{k+1}
+ * (differentiate eq. 3 under the integral sign):
+ *
+ *     grad_x[i] = - sum_{k=0..kmax} grad_f[i*ld_g + k] * F_{k+1}(x[i]).
+ *
+ * F_1..F_{kmax+1} are recomputed from x with the FP64 method at order
+ * kmax+1 (nothing is saved by the forward pass).
+ *
+ *   x       [n] FP64.   grad_f  row-major n x ld_g FP64, ld_g >= kmax + 1.
+ *   kmax    0 <= kmax <= 31.   grad_x [n] FP64 output.
+ * Errors as boys_eval_f64.
+ */
+BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax, int64_t ld_g,
+                  double *grad_x, hipStream_t stream);
+
+/* Releases the per-device workspaces and cached graphs of every device. */
+BOYS_API void boys_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOYS_H */

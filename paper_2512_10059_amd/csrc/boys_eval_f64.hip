@@ -1,0 +1,100 @@
+// boys_eval_f64: FP64 write-out of F_0..F_kmax (Algorithm 1, Sec. II F of
+// arXiv 2512.10059) on gfx950.
+//
+// One lane evaluates one argument with everything in VGPRs (boys_f64).  The
+// output row of an argument is kmax+1 contiguous doubles, so a wave's 64 rows
+// form one contiguous block of 64*(kmax+1) doubles; direct stores from the
+// lanes would hit 64 different cache lines per instruction.  Each wave
+// therefore stages its rows in its own LDS slice (row stride kmax+1 doubles,
+// which maps 16 consecutive lanes onto 32 distinct banks: conflict-free for
+// 64-bit writes) and writes the block back with 16-byte stores that cover
+// 1 KiB of consecutive addresses per instruction.  The stores are
+// non-temporal: the output is not re-read by this kernel.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <array>
+#include <utility>
+
+#include "boys.h"
+#include "boys_common.hpp"
+#include "boys_device_f64.hpp"
+
+namespace boys {
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ void store_nt(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restrict__ x, int64_t n,
+                                                          double *__restrict__ out, int64_t ld,
+                                                          int contiguous) {
+  constexpr int C = K + 1;
+  __shared__ __attribute__((aligned(16))) double stage[kWavesPerBlock * 64 * C];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double *slice = stage + wave * 64 * C;
+
+  for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
+    const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
+    const int64_t i = row0 + lane;
+    double F[C];
+    boys_f64<K>(i < n ? x[i] : 0.0, F);
+#pragma unroll
+    for (int l = 0; l < C; ++l) slice[lane * C + l] = F[l];
+    __syncthreads();
+    const int64_t rows = n - row0 < 64 ? n - row0 : 64;
+    if (contiguous && rows == 64) {
+      // 64*C doubles = 32*C 16-byte units, 64 lanes per instruction.
+      const d2 *src = reinterpret_cast<const d2 *>(slice);
+      d2 *dst = reinterpret_cast<d2 *>(out + row0 * C);
+#pragma unroll
+      for (int j = 0; j < (32 * C + 63) / 64; ++j) {
+        const int u = lane + 64 * j;
+        if (u < 32 * C) store_nt(dst + u, src[u]);
+      }
+    } else if (rows > 0) {
+      const int total = int(rows) * C;
+      for (int e = lane; e < total; e += 64) {
+        const int r = e / C, c = e - r * C;
+        store_nt(out + (row0 + r) * ld + c, slice[e]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+using EvalKernel = void (*)(const double *, int64_t, double *, int64_t, int);
+
+template <std::size_t... K>
+constexpr auto make_table(std::index_sequence<K...>) {
+  return std::array<EvalKernel, sizeof...(K)>{{&eval_f64_kernel<int(K)>...}};
+}
+constexpr auto kEvalTable = make_table(std::make_index_sequence<kF64Kmax + 1>{});
+
+}  // namespace
+}  // namespace boys
+
+extern "C" int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, int64_t ld_out,
+                             hipStream_t stream) {
+  using namespace boys;
+  if (n < 0 || kmax < 0 || kmax > kF64Kmax || ld_out < kmax + 1) return BOYS_EINVAL;
+  if (n == 0) return BOYS_OK;
+  if (!x || !out) return BOYS_EINVAL;
+  if (n - 1 > (INT64_MAX / 8 - (kmax + 1)) / ld_out) return BOYS_EINVAL;
+  const int64_t out_bytes = ((n - 1) * ld_out + kmax + 1) * 8;
+  if (overlaps(x, n * 8, out, out_bytes)) return BOYS_EINVAL;
+  if (int st = check_device()) return st;
+
+  const int contiguous = ld_out == kmax + 1 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > kMaxBlocks) blocks = kMaxBlocks;
+  hipLaunchKernelGGL(kEvalTable[kmax], dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x, n, out,
+                     ld_out, contiguous);
+  return hip_status(hipGetLastError());
+}

@@ -1,0 +1,61 @@
+// Status codes, error capture and device checks of libboys.so.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
+#include "boys.h"
+#include "boys_common.hpp"
+
+namespace boys {
+
+namespace {
+thread_local int g_last_hip_error = 0;
+constexpr int kMaxDevices = 64;
+// 0 = unknown, 1 = gfx950, -1 = other architecture.
+int g_arch_ok[kMaxDevices] = {0};
+std::mutex g_arch_mutex;
+}  // namespace
+
+int hip_status(hipError_t err) {
+  if (err == hipSuccess) return BOYS_OK;
+  g_last_hip_error = static_cast<int>(err);
+  return BOYS_EHIP;
+}
+
+int check_device() {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_status(err);
+  if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
+  {
+    std::lock_guard<std::mutex> lock(g_arch_mutex);
+    if (g_arch_ok[dev] != 0) return g_arch_ok[dev] > 0 ? BOYS_OK : BOYS_ENOTSUP;
+  }
+  hipDeviceProp_t prop;
+  err = hipGetDeviceProperties(&prop, dev);
+  if (err != hipSuccess) return hip_status(err);
+  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  std::lock_guard<std::mutex> lock(g_arch_mutex);
+  g_arch_ok[dev] = ok ? 1 : -1;
+  return ok ? BOYS_OK : BOYS_ENOTSUP;
+}
+
+}  // namespace boys
+
+extern "C" {
+
+const char *boys_strerror(int status) {
+  switch (status) {
+    case BOYS_OK: return "success";
+    case BOYS_EINVAL: return "invalid argument";
+    case BOYS_EHIP: return "HIP runtime error";
+    case BOYS_ENOTSUP: return "device not supported (libboys needs gfx950)";
+    case BOYS_ENOMEM: return "workspace allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int boys_last_hip_error(void) { return boys::g_last_hip_error; }
+
+}  // extern "C"

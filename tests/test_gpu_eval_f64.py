@@ -1,0 +1,146 @@
+"""boys_eval_f64 on the GPU against the CPU oracle (parity bar: 5e-14 absolute,
+the paper's guaranteed error for F_0..F_32 with its appendix tables)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_10059_amd as boys
+from paper_2512_10059_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS_TOL = 5e-14
+X0 = 11.899848152108484
+X1 = 28.98933773882074
+DEV = "cuda:0"
+
+
+def edge_arguments():
+    """Region boundaries and their neighbouring doubles, the oracle's own
+    branch switch, zeros, tiny and huge arguments."""
+    pts = [0.0, -0.0, 5e-324, 1e-300, 1e-12, 1e-6, 0.5, 1.0, 30.0, 1e3, 1e6, 1e300]
+    for b in (X0, X1):
+        v = b
+        for _ in range(4):
+            v = np.nextafter(v, -np.inf)
+        for _ in range(9):
+            pts.append(v)
+            v = np.nextafter(v, np.inf)
+    return np.array(pts)
+
+
+def run(x: np.ndarray, kmax: int) -> np.ndarray:
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    F = boys.boys_eval_f64(xt, kmax)
+    torch.cuda.synchronize()
+    return F.cpu().numpy()
+
+
+def assert_close(F, ref, tol=EPS_TOL, what=""):
+    err = np.abs(F - ref)
+    i = np.unravel_index(np.argmax(err), err.shape)
+    assert err.max() <= tol, f"{what} max abs err {err.max():.3e} at {i}"
+
+
+def test_mixed_workload_kmax8():
+    """N=65536 mixed arguments (0 / tiny / [0,1] / [1,30] / [30,1e4]), kmax=8,
+    every element against the oracle."""
+    x = workloads.mixed_arguments()
+    assert_close(run(x, 8), oracle.boys(x, 8), what="mixed kmax=8")
+
+
+@pytest.mark.parametrize("kmax", range(33))
+def test_every_order(kmax):
+    """Every kmax 0..32 over all three regions, the boundaries and a ragged
+    size (several 256-row tiles plus a partial wave)."""
+    rng = np.random.default_rng(100 + kmax)
+    x = np.concatenate([edge_arguments(), rng.uniform(0, X0, 900), rng.uniform(X0, X1, 500),
+                        np.exp(rng.uniform(np.log(X1), np.log(1e5), 400)),
+                        workloads.gaussian_pair_arguments(1200, seed=200 + kmax)])
+    rng.shuffle(x)
+    assert_close(run(x, kmax), oracle.boys(x, kmax), what=f"kmax={kmax}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1023, 4097])
+def test_ragged_sizes(n):
+    x = workloads.gaussian_pair_arguments(n, seed=7 + n)
+    assert_close(run(x, 32), oracle.boys(x, 32), what=f"n={n}")
+
+
+def test_empty_is_noop():
+    x = torch.empty(0, dtype=torch.float64, device=DEV)
+    F = boys.boys_eval_f64(x, 5)
+    assert F.shape == (0, 6)
+
+
+def test_padded_rows_and_unaligned_output():
+    """Row stride larger than kmax+1 leaves the padding untouched; an output
+    that is only 8-byte aligned takes the element-wise store path."""
+    x = workloads.gaussian_pair_arguments(1000, seed=9)
+    ref = oracle.boys(x, 12)
+    xt = torch.from_numpy(x).to(DEV)
+    big = torch.full((1000, 20), -7.0, dtype=torch.float64, device=DEV)
+    boys.boys_eval_f64(xt, 12, out=big[:, :13])
+    buf = torch.full((1000 * 13 + 1,), -7.0, dtype=torch.float64, device=DEV)
+    odd = buf[1:].view(1000, 13)
+    boys.boys_eval_f64(xt, 12, out=odd)
+    torch.cuda.synchronize()
+    b = big.cpu().numpy()
+    assert_close(b[:, :13], ref, what="padded")
+    assert np.all(b[:, 13:] == -7.0)
+    assert_close(odd.cpu().numpy(), ref, what="unaligned")
+    assert buf[0].item() == -7.0
+
+
+def test_domain_values():
+    x = np.array([-1.0, -1e-300, np.nan, np.inf, 0.0])
+    F = run(x, 10)
+    assert np.all(np.isnan(F[:3]))
+    assert np.all(F[3] == 0.0)
+    assert np.all(F[4] == oracle.boys([0.0], 10)[0]) or np.abs(F[4] - oracle.boys([0.0], 10)[0]).max() <= EPS_TOL
+
+
+def test_deterministic():
+    x = workloads.gaussian_pair_arguments(100000, seed=12)
+    a, b = run(x, 32), run(x, 32)
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_raise():
+    x = torch.ones(10, dtype=torch.float64, device=DEV)
+    with pytest.raises(boys.BoysError):
+        boys.boys_eval_f64(x, 33)
+    with pytest.raises(boys.BoysError):
+        boys.boys_eval_f64(x.float(), 3)
+    out = torch.empty((10, 5), dtype=torch.float64, device=DEV)
+    with pytest.raises(boys.BoysError):
+        boys.boys_eval_f64(x, 5, out=out)
+
+
+def test_full_writeout_workload_sampled():
+    """The write-out workload at full size (2^26 arguments, kmax=32, the launch
+    the benchmark times): 2^16 sampled rows plus the first and last 2048 rows
+    against the oracle, and on every row the bounds
+    e^-x/(2k+1) - tol <= F_k <= 1/(2k+1) + tol and F_k >= F_{k+1} - tol."""
+    x = workloads.gaussian_pair_arguments()
+    xt = torch.from_numpy(x).to(DEV)
+    F = boys.boys_eval_f64(xt, 32)
+    torch.cuda.synchronize()
+    n = x.size
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1 << 16), np.arange(2048),
+                                    np.arange(n - 2048, n)]))
+    Fs = F[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    assert_close(Fs, oracle.boys(x[idx], 32), what="write-out sample")
+    k = torch.arange(33, device=DEV, dtype=torch.float64)
+    inv = 1.0 / (2 * k + 1)
+    for s in range(0, n, 1 << 22):
+        blk = F[s:s + (1 << 22)]
+        xb = xt[s:s + (1 << 22)]
+        assert bool(torch.isfinite(blk).all())
+        assert bool((blk <= inv + EPS_TOL).all())
+        assert bool((blk >= torch.exp(-xb)[:, None] * inv - EPS_TOL).all())
+        assert bool((blk[:, 1:] <= blk[:, :-1] + EPS_TOL).all())
+    del F
+    torch.cuda.empty_cache()
