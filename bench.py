@@ -1,0 +1,323 @@
+#!/usr/bin/env python3
+"""Benchmark of the Boys-function library on one MI355X.
+
+Headline (one step = one write-out evaluation): F_0..F_32 in FP64 for 2^26
+Gaussian-pair arguments x = ab/(a+b) R^2, written as a row-major 2^26 x 33
+array (18.25 GB of algorithmic traffic per step).  The metric is Boys values
+per second, N (kmax+1) / time, at max abs error <= 5e-14.
+
+Beside the headline the same JSON line carries:
+  roofline      achieved GB/s of the write-out kernel (algorithmic bytes /
+                average launch time from HIP events) against 8 TB/s, and the
+                HBM traffic measured by rocprofv3 counters when the committed
+                counter summary matches the current kernel sources;
+  cpu_baseline  the long-double CPU oracle on the first 2^24 arguments
+                (all host cores), with the max abs error of the GPU rows there;
+  legs          FP32 vs FP64 at kmax=16 on the same arguments, the batched
+                fused consumer (8192 batches), and the differentiation pass
+                (2^24 arguments, kmax=16, forward + backward).
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--only writeout,fp32,fused,backward]
+       [--no-cpu-baseline] [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Boys values/s (x·(kmax+1)) at max abs err ≤5e-14 FP64; FP32 vs FP64 speedup"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "eval_f64_writeout_k32_n2e26_pmc.md")
+KERNEL_SOURCES = ["paper_2512_10059_amd/csrc/boys_eval_f64.hip",
+                  "paper_2512_10059_amd/csrc/boys_device_f64.hpp",
+                  "paper_2512_10059_amd/csrc/boys_coeffs_f64.h",
+                  "paper_2512_10059_amd/csrc/boys_common.hpp",
+                  "paper_2512_10059_amd/build.py"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic_bytes():
+    """HBM bytes per write-out launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    vals = dict(re.findall(r"^- (\w+): ([0-9.eE+-]+|[0-9a-f]+)\s*$", text, re.M))
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_scale"])
+        write = float(vals["write_kib_per_dispatch"]) * float(vals["write_scale"])
+    except KeyError:
+        return None
+    return (fetch + write) * 1024.0
+
+
+class Timer:
+    """HIP events on the current (launch) stream around a region."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.torch.cuda.synchronize()
+        self.wall = time.perf_counter() - self.t0
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def leg_writeout(torch, boys, workloads, steps, warmup, dev):
+    n, kmax = workloads.N_WRITEOUT, 32
+    log(f"write-out: generating {n} arguments")
+    x_host = workloads.gaussian_pair_arguments(n)
+    x = torch.from_numpy(x_host).to(dev)
+    out = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        boys.boys_eval_f64(x, kmax, out=out)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            boys.boys_eval_f64(x, kmax, out=out)
+    ms = t.ms / steps
+    alg_bytes = n * 8 * (kmax + 2)
+    log(f"write-out: {ms:.3f} ms/step, {alg_bytes / ms / 1e6:.0f} GB/s")
+    return dict(x_host=x_host, x=x, out=out, ms=ms, wall=t.wall, n=n, kmax=kmax,
+                alg_bytes=alg_bytes)
+
+
+def leg_fp32(torch, boys, workloads, steps, warmup, dev, x_host=None):
+    n, kmax = workloads.N_WRITEOUT, 16
+    if x_host is None:
+        x_host = workloads.gaussian_pair_arguments(n)
+    x32 = torch.from_numpy(x_host.astype(np.float32)).to(dev)
+    x64 = x32.double()
+    o32 = torch.empty((n, kmax + 1), dtype=torch.float32, device=dev)
+    o64 = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    res = {}
+    for name, fn, xx, oo in (("f32", boys.boys_eval_f32, x32, o32), ("f64", boys.boys_eval_f64, x64, o64)):
+        for _ in range(warmup):
+            fn(xx, kmax, out=oo)
+        with Timer(torch) as t:
+            for _ in range(steps):
+                fn(xx, kmax, out=oo)
+        res[name] = t.ms / steps
+    b32, b64 = n * 4 * (kmax + 2), n * 8 * (kmax + 2)
+    log(f"fp32: {res['f32']:.3f} ms vs fp64 {res['f64']:.3f} ms")
+    return {"n": n, "kmax": kmax, "ms_f32": res["f32"], "ms_f64": res["f64"],
+            "speedup_f32_vs_f64": res["f64"] / res["f32"],
+            "values_per_s_f32": n * (kmax + 1) / (res["f32"] * 1e-3),
+            "gbs_f32": b32 / (res["f32"] * 1e6), "gbs_f64": b64 / (res["f64"] * 1e6),
+            "_x32": x32, "_o32": o32}
+
+
+def algorithmic_flops(x, k, deg_nm):
+    """Operation count of the method per argument (FMA = 2, exp, sqrt and
+    division = 1 each): region A 2(n_k+m_k) + 2 + 3k, region B 25 + 3k,
+    region C 2 + 2k; the fused consumer adds 2(k+1) for the weighted sum."""
+    X0, X1 = 11.899848152108484, 28.98933773882074
+    a = x < X0
+    c = x > X1
+    b = ~a & ~c
+    nm = np.array([n + m for n, m in deg_nm])[k]
+    return (a * (2 * nm + 2 + 3 * k) + b * (25 + 3 * k) + c * (2 + 2 * k) + 2 * (k + 1)).sum()
+
+
+def leg_fused(torch, boys, workloads, steps, warmup, dev):
+    bt = workloads.batched_workload()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    args = (t(bt.x), t(bt.batch_off), t(bt.batch_n), t(bt.batch_kmax), t(bt.w), t(bt.w_off))
+    out = torch.zeros_like(args[0])
+    cfg, tune_ms, name = boys.boys_tune_weighted_sum(*args, out=out)
+    for _ in range(warmup):
+        boys.boys_weighted_sum(*args, out=out)
+    with Timer(torch) as tm:
+        for _ in range(steps):
+            boys.boys_weighted_sum(*args, out=out)
+    ms = tm.ms / steps
+    kk = np.repeat(bt.batch_kmax.astype(np.int64), bt.batch_n.astype(np.int64))
+    values = int((kk + 1).sum())
+    from paper_2512_10059_amd.tables import f64_region_a_degrees
+    flops = float(algorithmic_flops(bt.x, kk, f64_region_a_degrees()))
+    nbytes = bt.x.size * 16 + bt.w.size * 8 + bt.batch_n.size * 24
+    log(f"fused: {ms:.3f} ms, config {name}")
+    return {"nbatch": int(bt.batch_n.size), "arguments": int(bt.x.size), "values": values,
+            "ms": ms, "config": name, "tune_ms": tune_ms,
+            "values_per_s": values / (ms * 1e-3),
+            "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp64_peak_frac_algorithmic": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "gbs": nbytes / (ms * 1e6)}
+
+
+def leg_backward(torch, boys, workloads, steps, warmup, dev):
+    n, kmax = workloads.N_BACKWARD, 16
+    x_host, G_host = workloads.backward_workload(n=n, kmax=kmax)
+    x = torch.from_numpy(x_host).to(dev)
+    G = torch.from_numpy(G_host).to(dev)
+    F = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    g = torch.empty_like(x)
+    for _ in range(warmup):
+        boys.boys_eval_f64(x, kmax, out=F)
+        boys.boys_backward(x, G, kmax, out=g)
+    with Timer(torch) as tf:
+        for _ in range(steps):
+            boys.boys_eval_f64(x, kmax, out=F)
+    with Timer(torch) as tb:
+        for _ in range(steps):
+            boys.boys_backward(x, G, kmax, out=g)
+    fms, bms = tf.ms / steps, tb.ms / steps
+    log(f"backward: forward {fms:.3f} ms, backward {bms:.3f} ms")
+    return {"n": n, "kmax": kmax, "ms_forward": fms, "ms_backward": bms,
+            "gbs_forward": n * 8 * (kmax + 2) / (fms * 1e6),
+            "gbs_backward": n * 8 * (kmax + 3) / (bms * 1e6)}
+
+
+def cpu_baseline_leg(torch, wo, fp32):
+    """The oracle on the first 2^24 write-out arguments, all host cores; the
+    GPU rows of the same arguments are compared with it on the way."""
+    import oracle
+    m = 1 << 24
+    chunk = 1 << 21
+    threads = oracle.max_threads()
+    err = 0.0
+    t_cpu = 0.0
+    for s in range(0, m, chunk):
+        xs = wo["x_host"][s:s + chunk]
+        t0 = time.perf_counter()
+        ref = oracle.boys(xs, 32, threads=threads)
+        t_cpu += time.perf_counter() - t0
+        got = wo["out"][s:s + chunk].cpu().numpy()
+        err = max(err, float(np.abs(got - ref).max()))
+    res = {"value": m * 33 / t_cpu, "unit": "values/s", "cores": threads, "kind": "oracle",
+           "sample": f"first 2^24 of the 2^26 write-out arguments, kmax=32, long-double oracle, "
+                     f"{threads} threads, {t_cpu:.1f} s",
+           "gpu_max_abs_err_on_sample": err}
+    if fp32 is not None:
+        # FP32 path against the FP64 oracle at the FP32-rounded arguments.
+        xs = fp32["_x32"][:1 << 20].cpu().numpy().astype(np.float64)
+        ref = oracle.boys(xs, 16, threads=threads)
+        got = fp32["_o32"][:1 << 20].cpu().numpy().astype(np.float64)
+        res["fp32_max_abs_err_on_2^20"] = float(np.abs(got - ref).max())
+    log(f"cpu baseline: {res['value']:.3e} values/s on {threads} threads; GPU max err {err:.2e}")
+    return res
+
+
+def copy_probe(torch, dev):
+    """A plain elementwise copy of known size, for calibrating HBM counters."""
+    n = 1 << 29  # 4 GiB read + 4 GiB written per launch
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", default="writeout,fp32,fused,backward")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); every argument "
+              "is independent, so the path would shard by contiguous slices, but no multi-GPU "
+              "run is implemented here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2512_10059_amd as boys
+    from paper_2512_10059_amd import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe:
+        copy_probe(torch, dev)
+        return
+    legs = set(args.only.split(","))
+    wo = leg_writeout(torch, boys, workloads, args.steps, args.warmup, dev)
+    extra = {}
+    fp32 = None
+    if "fp32" in legs:
+        try:
+            fp32 = leg_fp32(torch, boys, workloads, args.steps, args.warmup, dev, wo["x_host"])
+            extra["fp32"] = {k: v for k, v in fp32.items() if not k.startswith("_")}
+        except Exception as e:  # reported, not hidden
+            extra["fp32"] = {"error": str(e)}
+    if "fused" in legs:
+        try:
+            extra["fused"] = leg_fused(torch, boys, workloads, args.steps, args.warmup, dev)
+        except Exception as e:
+            extra["fused"] = {"error": str(e)}
+    if "backward" in legs:
+        try:
+            extra["backward"] = leg_backward(torch, boys, workloads, args.steps, args.warmup, dev)
+        except Exception as e:
+            extra["backward"] = {"error": str(e)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_leg(torch, wo, fp32)
+
+    ms = wo["ms"]
+    achieved = wo["alg_bytes"] / (ms * 1e-3) / 1e9
+    traffic = pmc_traffic_bytes()
+    line = {
+        "metric": METRIC,
+        "value": wo["n"] * (wo["kmax"] + 1) / (ms * 1e-3),
+        "unit": "values/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "write-out F_0..F_32 of 2^26 Gaussian-pair arguments "
+                               "x=ab/(a+b)R^2 (a,b log-uniform [0.05,1e4], R uniform [0,8]), "
+                               "row-major 2^26 x 33 FP64",
+                   "n": wo["n"], "kmax": wo["kmax"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "eval_f64_kernel<32>",
+                     "algorithmic_bytes_per_launch": wo["alg_bytes"]},
+        "cpu_baseline": cpu,
+        "legs": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,89 @@
+// boys_backward: gradient of F_0..F_kmax with respect to x on gfx950.
+//
+// dF_k/dx = -F_{k+1} (differentiate the defining integral under the integral
+// sign), so for upstream gradients G
+//
+//     grad_x[i] = - sum_{k=0..kmax} G[i, k] F_{k+1}(x[i]).
+//
+// The kernel recomputes F_0..F_{kmax+1} in VGPRs with the FP64 method at
+// order kmax+1 instead of reading values saved by the forward pass: x is
+// 8 bytes per argument while the saved rows would be 8*(kmax+1).  G rows are
+// the dominant traffic (8*(kmax+1) bytes per argument); each wave reads its
+// 64 rows as one contiguous stream into an LDS slice whose row stride is
+// padded to an odd number of doubles, so that the per-lane row reads that
+// follow are free of bank conflicts.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <utility>
+
+#include "boys.h"
+#include "boys_common.hpp"
+#include "boys_device_f64.hpp"
+
+namespace boys {
+namespace {
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restrict__ x,
+                                                          const double *__restrict__ g, int64_t n,
+                                                          int64_t ld, double *__restrict__ grad) {
+  constexpr int C = K + 1;                  // columns of G used
+  constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // padded LDS row stride
+  __shared__ double stage[kWavesPerBlock * 64 * CP];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double *slice = stage + wave * 64 * CP;
+
+  for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
+    const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
+    const int64_t i = row0 + lane;
+    const int rows = n - row0 < 64 ? int(n - row0 > 0 ? n - row0 : 0) : 64;
+    // This wave's rows of G, 64 consecutive doubles per load instruction.
+    for (int e = lane; e < rows * C; e += 64) {
+      const int r = e / C, c = e - r * C;
+      slice[r * CP + c] = __builtin_nontemporal_load(g + (row0 + r) * ld + c);
+    }
+    double F[C + 1];
+    boys_f64<K + 1>(i < n ? x[i] : 0.0, F);
+    __syncthreads();
+    if (i < n) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < C; ++k) acc = __builtin_fma(slice[lane * CP + k], F[k + 1], acc);
+      grad[i] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+using BackwardKernel = void (*)(const double *, const double *, int64_t, int64_t, double *);
+
+template <std::size_t... K>
+constexpr auto make_table(std::index_sequence<K...>) {
+  return std::array<BackwardKernel, sizeof...(K)>{{&backward_kernel<int(K)>...}};
+}
+constexpr auto kBackwardTable = make_table(std::make_index_sequence<kF64Kmax>{});
+
+}  // namespace
+}  // namespace boys
+
+extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax,
+                             int64_t ld_g, double *grad_x, hipStream_t stream) {
+  using namespace boys;
+  if (n < 0 || kmax < 0 || kmax > kF64Kmax - 1 || ld_g < kmax + 1) return BOYS_EINVAL;
+  if (n == 0) return BOYS_OK;
+  if (!x || !grad_f || !grad_x) return BOYS_EINVAL;
+  if (n - 1 > (INT64_MAX / 8 - (kmax + 1)) / ld_g) return BOYS_EINVAL;
+  const int64_t g_bytes = ((n - 1) * ld_g + kmax + 1) * 8;
+  if (overlaps(grad_x, n * 8, x, n * 8) || overlaps(grad_x, n * 8, grad_f, g_bytes))
+    return BOYS_EINVAL;
+  if (int st = check_device()) return st;
+
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > kMaxBlocks) blocks = kMaxBlocks;
+  hipLaunchKernelGGL(kBackwardTable[kmax], dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x,
+                     grad_f, n, ld_g, grad_x);
+  return hip_status(hipGetLastError());
+}

@@ -91,3 +91,84 @@ __device__ __forceinline__ void boys_f64(double x, double (&F)[K + 1]) {
 }
 
 }  // namespace boys
+
+namespace boys {
+
+// ---------------------------------------------------------------------------
+// Runtime-order variants for kernels whose order k is uniform per tile but
+// not a compile-time constant (the batched consumer).  The arithmetic is the
+// same as boys_f64<K>, step for step.
+
+// r_{A,k}(x) for a wave-uniform k in [0, 32] (a jump on a scalar register).
+__device__ __forceinline__ double rational_a_rt(double x, int k) {
+  switch (k) {
+#define BOYS_RA_CASE(K) \
+  case K:               \
+    return rational_a<K>(x);
+    BOYS_RA_CASE(0) BOYS_RA_CASE(1) BOYS_RA_CASE(2) BOYS_RA_CASE(3) BOYS_RA_CASE(4)
+    BOYS_RA_CASE(5) BOYS_RA_CASE(6) BOYS_RA_CASE(7) BOYS_RA_CASE(8) BOYS_RA_CASE(9)
+    BOYS_RA_CASE(10) BOYS_RA_CASE(11) BOYS_RA_CASE(12) BOYS_RA_CASE(13) BOYS_RA_CASE(14)
+    BOYS_RA_CASE(15) BOYS_RA_CASE(16) BOYS_RA_CASE(17) BOYS_RA_CASE(18) BOYS_RA_CASE(19)
+    BOYS_RA_CASE(20) BOYS_RA_CASE(21) BOYS_RA_CASE(22) BOYS_RA_CASE(23) BOYS_RA_CASE(24)
+    BOYS_RA_CASE(25) BOYS_RA_CASE(26) BOYS_RA_CASE(27) BOYS_RA_CASE(28) BOYS_RA_CASE(29)
+    BOYS_RA_CASE(30) BOYS_RA_CASE(31) BOYS_RA_CASE(32)
+#undef BOYS_RA_CASE
+    default:
+      return __builtin_nan("");
+  }
+}
+
+// sum_{l=0..k} w[l] F_l(x) on region A: r_{A,k}, then the downward
+// recurrence with the weighted sum accumulated inside it, as in the paper's
+// benchmark consumer (Sec. III, Algorithm 2).  The recurrence enters an
+// unrolled ladder at step k (so every 1/(2l+1) is a literal and every w[l]
+// an LDS read at a constant offset).
+__device__ __forceinline__ double wsum_region_a(double x, int k, const double *w) {
+  const double e = ::exp(-x);
+  const double two_x = x + x;
+  double F = rational_a_rt(x, k);
+  double acc = w[k] * F;
+  switch (k) {
+#define BOYS_DOWN(L)                                          \
+  case L + 1:                                                 \
+    F = __builtin_fma(two_x, F, e) * (1.0 / (2 * (L) + 1));  \
+    acc = __builtin_fma(w[L], F, acc);                        \
+    [[fallthrough]];
+    BOYS_DOWN(31) BOYS_DOWN(30) BOYS_DOWN(29) BOYS_DOWN(28) BOYS_DOWN(27) BOYS_DOWN(26)
+    BOYS_DOWN(25) BOYS_DOWN(24) BOYS_DOWN(23) BOYS_DOWN(22) BOYS_DOWN(21) BOYS_DOWN(20)
+    BOYS_DOWN(19) BOYS_DOWN(18) BOYS_DOWN(17) BOYS_DOWN(16) BOYS_DOWN(15) BOYS_DOWN(14)
+    BOYS_DOWN(13) BOYS_DOWN(12) BOYS_DOWN(11) BOYS_DOWN(10) BOYS_DOWN(9) BOYS_DOWN(8)
+    BOYS_DOWN(7) BOYS_DOWN(6) BOYS_DOWN(5) BOYS_DOWN(4) BOYS_DOWN(3) BOYS_DOWN(2)
+    BOYS_DOWN(1) BOYS_DOWN(0)
+#undef BOYS_DOWN
+    default:
+      break;
+  }
+  return acc;
+}
+
+// Upward pass with the weighted sum: F_{l+1} = ((2l+1) F_l - e) / (2x),
+// from F_0 = f0; e = e^-x on region B and 0 on region C.
+__device__ __forceinline__ double wsum_upward(double x, double f0, double e, int k,
+                                              const double *w) {
+  const double inv_2x = 0.5 / x;
+  double F = f0;
+  double acc = w[0] * F;
+#pragma unroll
+  for (int l = 0; l < kF64Kmax; ++l) {
+    if (l >= k) break;
+    F = __builtin_fma(double(2 * l + 1), F, -e) * inv_2x;
+    acc = __builtin_fma(w[l + 1], F, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double wsum_region_b(double x, int k, const double *w) {
+  return wsum_upward(x, rational_b(x), ::exp(-x), k, w);
+}
+
+__device__ __forceinline__ double wsum_region_c(double x, int k, const double *w) {
+  return wsum_upward(x, kHalfSqrtPi / ::sqrt(x), 0.0, k, w);
+}
+
+}  // namespace boys

@@ -5,11 +5,11 @@
 // output row of an argument is kmax+1 contiguous doubles, so a wave's 64 rows
 // form one contiguous block of 64*(kmax+1) doubles; direct stores from the
 // lanes would hit 64 different cache lines per instruction.  Each wave
-// therefore stages its rows in its own LDS slice (row stride kmax+1 doubles,
-// which maps 16 consecutive lanes onto 32 distinct banks: conflict-free for
-// 64-bit writes) and writes the block back with 16-byte stores that cover
-// 1 KiB of consecutive addresses per instruction.  The stores are
-// non-temporal: the output is not re-read by this kernel.
+// therefore stages its rows in its own LDS slice and writes the block back
+// with 16-byte stores that cover 1 KiB of consecutive addresses per
+// instruction.  The LDS row stride is the odd number kmax+1 or kmax+2, which
+// maps 16 consecutive lanes onto 32 distinct banks (conflict-free 64-bit
+// writes).  The stores are non-temporal: nothing re-reads the output here.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,11 +34,12 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restrict__ x, int64_t n,
                                                           double *__restrict__ out, int64_t ld,
                                                           int contiguous) {
-  constexpr int C = K + 1;
-  __shared__ __attribute__((aligned(16))) double stage[kWavesPerBlock * 64 * C];
+  constexpr int C = K + 1;                      // doubles per output row
+  constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // LDS row stride (odd)
+  __shared__ __attribute__((aligned(16))) double stage[kWavesPerBlock * 64 * CP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  double *slice = stage + wave * 64 * C;
+  double *slice = stage + wave * 64 * CP;
 
   for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
     const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
@@ -46,23 +47,31 @@ __global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restri
     double F[C];
     boys_f64<K>(i < n ? x[i] : 0.0, F);
 #pragma unroll
-    for (int l = 0; l < C; ++l) slice[lane * C + l] = F[l];
+    for (int l = 0; l < C; ++l) slice[lane * CP + l] = F[l];
     __syncthreads();
     const int64_t rows = n - row0 < 64 ? n - row0 : 64;
     if (contiguous && rows == 64) {
-      // 64*C doubles = 32*C 16-byte units, 64 lanes per instruction.
-      const d2 *src = reinterpret_cast<const d2 *>(slice);
+      // The wave's 64 rows are 64*C contiguous doubles = 32*C 16-byte units.
       d2 *dst = reinterpret_cast<d2 *>(out + row0 * C);
 #pragma unroll
       for (int j = 0; j < (32 * C + 63) / 64; ++j) {
         const int u = lane + 64 * j;
-        if (u < 32 * C) store_nt(dst + u, src[u]);
+        if (u < 32 * C) {
+          d2 v;
+          if constexpr (CP == C) {
+            v = reinterpret_cast<const d2 *>(slice)[u];
+          } else {  // even C: a unit never straddles two rows
+            const int r = (2 * u) / C, c = 2 * u - r * C;
+            v = d2{slice[r * CP + c], slice[r * CP + c + 1]};
+          }
+          store_nt(dst + u, v);
+        }
       }
     } else if (rows > 0) {
       const int total = int(rows) * C;
       for (int e = lane; e < total; e += 64) {
         const int r = e / C, c = e - r * C;
-        store_nt(out + (row0 + r) * ld + c, slice[e]);
+        store_nt(out + (row0 + r) * ld + c, slice[r * CP + c]);
       }
     }
     __syncthreads();

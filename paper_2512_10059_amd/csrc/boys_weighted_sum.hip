@@ -1,0 +1,575 @@
+// boys_weighted_sum: batched fused consumer on gfx950.
+//
+// For every batch b (size n_b, order k_b, weights w_b) and every argument i of
+// it:  out[i] = sum_{l=0..k_b} w_{b,l} F_l(x[i]), the weighted sum the paper's
+// benchmark accumulates inside the recurrence (Sec. III, Algorithm 2).
+//
+// Work decomposition.  Each batch is cut into tiles of T = 256*ITEMS
+// arguments; a tile has one order, so the recurrence length is uniform over
+// it.  A one-block scan kernel turns the batch table into two prefix sums:
+// tiles and cost, where a tile of batch b costs k_b + kCostBias units (the
+// recurrence plus the per-argument work before it).  The persistent kernel
+// then runs a fixed grid of a few workgroups per CU; workgroup g takes the
+// tiles whose cost prefix falls in [g, g+1) * total / grid, i.e. a contiguous
+// run of tiles of about equal cost, walking the batches in order.  There is no
+// shared counter, so the result is deterministic and no memory has to be
+// reset between launches.
+//
+// Divergence.  Argument streams mix all three regions inside every wave, and
+// Algorithm 1 takes a different path in each.  With binning enabled the tile
+// is first sorted by region in LDS (wave-aggregated LDS atomics), so every
+// wave except at most two runs a single path; results are scattered back to
+// their original positions inside the tile.
+//
+// The scan and the persistent kernel are launched as one cached hipGraph per
+// device; the graph is rebuilt when any argument or the configuration
+// changes.  The batch table is read on the device by the graph itself, so
+// changing its contents in place is safe.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "boys.h"
+#include "boys_common.hpp"
+#include "boys_device_f64.hpp"
+
+namespace boys {
+namespace {
+
+constexpr int kCostBias = 8;
+constexpr int kScanThreads = 1024;
+constexpr int32_t kMaxBatches = 1 << 24;
+
+struct WsArgs {
+  const double *x;
+  const int64_t *boff;
+  const int32_t *bn;
+  const int32_t *bk;
+  const double *w;
+  const int64_t *woff;
+  double *out;
+  const int64_t *tile_start;  // [nbatch+1]
+  const int64_t *cost_start;  // [nbatch+1]
+  int32_t nbatch;
+};
+
+__device__ __forceinline__ int clamp_order(int k) { return k < 0 ? 0 : (k > kF64Kmax ? kF64Kmax : k); }
+
+// Exclusive prefix sums of tiles and cost over the batches (one workgroup).
+__global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__restrict__ bn,
+                                                               const int32_t *__restrict__ bk,
+                                                               int32_t nbatch, int tile,
+                                                               int64_t *__restrict__ tile_start,
+                                                               int64_t *__restrict__ cost_start) {
+  __shared__ int64_t s_t[kScanThreads], s_c[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (int64_t(nbatch) + kScanThreads - 1) / kScanThreads;
+  const int64_t lo = tid * chunk;
+  const int64_t hi = lo + chunk < nbatch ? lo + chunk : nbatch;
+  int64_t st = 0, sc = 0;
+  for (int64_t b = lo; b < hi; ++b) {
+    const int64_t n = bn[b] > 0 ? bn[b] : 0;
+    const int64_t t = (n + tile - 1) / tile;
+    st += t;
+    sc += t * (clamp_order(bk[b]) + kCostBias);
+  }
+  s_t[tid] = st;
+  s_c[tid] = sc;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t at = tid >= off ? s_t[tid - off] : 0;
+    const int64_t ac = tid >= off ? s_c[tid - off] : 0;
+    __syncthreads();
+    s_t[tid] += at;
+    s_c[tid] += ac;
+    __syncthreads();
+  }
+  st = s_t[tid] - st;  // exclusive
+  sc = s_c[tid] - sc;
+  for (int64_t b = lo; b < hi; ++b) {
+    tile_start[b] = st;
+    cost_start[b] = sc;
+    const int64_t n = bn[b] > 0 ? bn[b] : 0;
+    const int64_t t = (n + tile - 1) / tile;
+    st += t;
+    sc += t * (clamp_order(bk[b]) + kCostBias);
+  }
+  if (tid == kScanThreads - 1) {
+    tile_start[nbatch] = s_t[tid];
+    cost_start[nbatch] = s_c[tid];
+  }
+}
+
+// Per-workgroup walk state, kept by thread 0 and broadcast through LDS.
+struct TileInfo {
+  int64_t first;  // index of the tile's first argument
+  int32_t count;  // arguments in the tile
+  int32_t order;  // k_b
+  int32_t done;
+};
+
+template <int ITEMS, bool BIN>
+__global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
+  constexpr int T = kBlock * ITEMS;
+  __shared__ double s_w[kF64Kmax + 1];
+  __shared__ double s_x[BIN ? T : 1];
+  __shared__ int s_idx[BIN ? T : 1];
+  __shared__ int s_count[3], s_fill[3];
+  __shared__ TileInfo s_info;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+
+  // Thread 0's walk state: batch b, tile j within it.
+  int32_t b = 0;
+  int64_t j = 0, tiles_b = 0, cs_b = 0, cost_b = 0, hi = 0;
+  int32_t n_b = 0, k_b = 0;
+  int64_t off_b = 0, woff_b = 0;
+  bool load_weights = true;
+
+  if (tid == 0) {
+    const int64_t total = a.cost_start[a.nbatch];
+    const int64_t lo = total * int64_t(blockIdx.x) / gridDim.x;
+    hi = total * int64_t(blockIdx.x + 1) / gridDim.x;
+    // Largest b with cost_start[b] <= lo.
+    int32_t l = 0, h = a.nbatch;
+    while (l < h) {
+      const int32_t m = (l + h + 1) >> 1;
+      if (a.cost_start[m] <= lo) l = m; else h = m - 1;
+    }
+    b = l;
+    if (b < a.nbatch) {
+      cs_b = a.cost_start[b];
+      tiles_b = a.tile_start[b + 1] - a.tile_start[b];
+      k_b = clamp_order(a.bk[b]);
+      cost_b = k_b + kCostBias;
+      j = (lo - cs_b + cost_b - 1) / cost_b;
+    }
+  }
+
+  for (;;) {
+    if (tid == 0) {
+      // Move past finished and empty batches.
+      while (b < a.nbatch && j >= tiles_b) {
+        ++b;
+        j = 0;
+        load_weights = true;
+        if (b < a.nbatch) {
+          cs_b = a.cost_start[b];
+          tiles_b = a.tile_start[b + 1] - a.tile_start[b];
+          k_b = clamp_order(a.bk[b]);
+          cost_b = k_b + kCostBias;
+        }
+      }
+      const bool done = b >= a.nbatch || cs_b + j * cost_b >= hi;
+      s_info.done = done;
+      if (!done) {
+        if (load_weights) {
+          n_b = a.bn[b];
+          off_b = a.boff[b];
+          woff_b = a.woff[b];
+          for (int l = 0; l <= k_b; ++l) s_w[l] = a.w[woff_b + l];
+          load_weights = false;
+        }
+        s_info.first = off_b + j * T;
+        const int64_t rem = int64_t(n_b) - j * T;
+        s_info.count = int32_t(rem < T ? rem : T);
+        s_info.order = k_b;
+      }
+      ++j;
+    }
+    if (BIN && tid < 3) s_count[tid] = 0;
+    __syncthreads();
+    if (s_info.done) break;
+    const int64_t first = s_info.first;
+    const int count = s_info.count;
+    const int k = s_info.order;
+
+    if constexpr (BIN) {
+      double xv[ITEMS];
+      int cls[ITEMS];
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const int p = it * kBlock + tid;
+        xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
+        cls[it] = p >= count ? 3 : (xv[it] < kX0 ? 0 : (region_c(xv[it]) ? 2 : 1));
+      }
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const uint64_t m = __ballot(cls[it] == c);
+          if (lane == 0 && m) atomicAdd(&s_count[c], __popcll(m));
+        }
+      __syncthreads();
+      if (tid < 3) s_fill[tid] = tid == 0 ? 0 : (tid == 1 ? s_count[0] : s_count[0] + s_count[1]);
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const uint64_t m = __ballot(cls[it] == c);
+          if (!m) continue;
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&s_fill[c], __popcll(m));
+          base = __builtin_amdgcn_readfirstlane(base);
+          if (cls[it] == c) {
+            const int below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
+            s_x[base + below] = xv[it];
+            s_idx[base + below] = it * kBlock + tid;
+          }
+        }
+      __syncthreads();
+      const int nA = s_count[0], nAB = s_count[0] + s_count[1];
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const int q = it * kBlock + tid;
+        if (q < count) {
+          const double xq = s_x[q];
+          double acc;
+          if (q < nA) acc = wsum_region_a(xq, k, s_w);
+          else if (q < nAB) acc = wsum_region_b(xq, k, s_w);
+          else acc = wsum_region_c(xq, k, s_w);
+          a.out[first + s_idx[q]] = acc;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const int p = it * kBlock + tid;
+        if (p < count) {
+          const double xq = domain(a.x[first + p]);
+          double acc;
+          if (xq < kX0) acc = wsum_region_a(xq, k, s_w);
+          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_w);
+          else acc = wsum_region_b(xq, k, s_w);
+          a.out[first + p] = acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Configurations (the autotuner's search space).
+
+using WsKernel = void (*)(WsArgs);
+
+struct WsConfig {
+  WsKernel kernel;
+  int items;        // arguments per thread per tile (tile = 256 * items)
+  int bin;          // region binning in LDS
+  int blocks_per_cu;
+  const char *name;
+};
+
+const WsConfig kConfigs[] = {
+    {&ws_kernel<1, true>, 1, 1, 8, "tile256-bin-8wg"},
+    {&ws_kernel<2, true>, 2, 1, 4, "tile512-bin-4wg"},
+    {&ws_kernel<2, true>, 2, 1, 8, "tile512-bin-8wg"},
+    {&ws_kernel<4, true>, 4, 1, 4, "tile1024-bin-4wg"},
+    {&ws_kernel<4, true>, 4, 1, 8, "tile1024-bin-8wg"},
+    {&ws_kernel<1, false>, 1, 0, 8, "tile256-nobin-8wg"},
+    {&ws_kernel<2, false>, 2, 0, 8, "tile512-nobin-8wg"},
+    {&ws_kernel<4, false>, 4, 0, 4, "tile1024-nobin-4wg"},
+};
+constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
+constexpr int kDefaultConfig = 2;
+
+// ---------------------------------------------------------------------------
+// Per-device state: workspace, cached graph, chosen configuration.
+
+struct GraphKey {
+  const void *ptrs[7];
+  int32_t nbatch;
+  int config;
+  const void *ws;
+  bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct DeviceState {
+  std::mutex mu;
+  int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
+  int64_t ws_cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GraphKey key;
+  bool has_key = false;
+  int config = -1;  // -1: not chosen yet
+  int cus = 0;
+};
+
+constexpr int kMaxDevices = 64;
+DeviceState g_dev[kMaxDevices];
+
+void drop_graph(DeviceState &s) {
+  if (s.exec) (void)hipGraphExecDestroy(s.exec);
+  if (s.graph) (void)hipGraphDestroy(s.graph);
+  s.exec = nullptr;
+  s.graph = nullptr;
+  s.has_key = false;
+}
+
+// Configuration from the tuning cache file named by BOYS_TUNE_CACHE (lines
+// "weighted_sum <log2 nbatch> <config>"), else the default.
+int cached_config(int32_t nbatch) {
+  const char *path = std::getenv("BOYS_TUNE_CACHE");
+  int best = kDefaultConfig;
+  if (!path) return best;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return best;
+  const int bucket = nbatch > 0 ? int(std::log2(double(nbatch))) : 0;
+  char name[64];
+  int bk = 0, cfg = 0;
+  while (std::fscanf(f, "%63s %d %d", name, &bk, &cfg) == 3)
+    if (std::strcmp(name, "weighted_sum") == 0 && bk == bucket && cfg >= 0 && cfg < kNumConfigs)
+      best = cfg;
+  std::fclose(f);
+  return best;
+}
+
+void store_config(int32_t nbatch, int cfg) {
+  const char *path = std::getenv("BOYS_TUNE_CACHE");
+  if (!path) return;
+  if (FILE *f = std::fopen(path, "a")) {
+    std::fprintf(f, "weighted_sum %d %d\n", nbatch > 0 ? int(std::log2(double(nbatch))) : 0, cfg);
+    std::fclose(f);
+  }
+}
+
+struct Call {
+  const double *x;
+  const int64_t *boff;
+  const int32_t *bn;
+  const int32_t *bk;
+  const double *w;
+  const int64_t *woff;
+  int32_t nbatch;
+  double *out;
+};
+
+// Makes sure the workspace holds 2*(nbatch+1) entries.
+int ensure_workspace(DeviceState &s, int32_t nbatch) {
+  const int64_t need = int64_t(nbatch) + 1;
+  if (s.ws_cap >= need) return BOYS_OK;
+  if (s.ws) {
+    // An earlier graph may still be reading the old workspace.
+    BOYS_TRY_HIP(hipDeviceSynchronize());
+    BOYS_TRY_HIP(hipFree(s.ws));
+    s.ws = nullptr;
+    s.ws_cap = 0;
+  }
+  drop_graph(s);
+  int64_t cap = 1024;
+  while (cap < need) cap *= 2;
+  if (hipMalloc(&s.ws, size_t(2 * cap) * sizeof(int64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    s.ws = nullptr;
+    return BOYS_ENOMEM;
+  }
+  s.ws_cap = cap;
+  return BOYS_OK;
+}
+
+// Builds (or reuses) the graph {scan -> persistent kernel} for this call.
+int prepare_graph(DeviceState &s, const Call &c, int cfg) {
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  const void *p[7] = {c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out};
+  std::memcpy(key.ptrs, p, sizeof(p));
+  key.nbatch = c.nbatch;
+  key.config = cfg;
+  key.ws = s.ws;
+  if (s.has_key && s.exec && key == s.key) return BOYS_OK;
+  drop_graph(s);
+
+  const WsConfig &conf = kConfigs[cfg];
+  int64_t *tile_start = s.ws;
+  int64_t *cost_start = s.ws + s.ws_cap;
+  int tile = kBlock * conf.items;
+
+  BOYS_TRY_HIP(hipGraphCreate(&s.graph, 0));
+  hipGraphNode_t scan_node, main_node;
+
+  const int32_t *bn = c.bn, *bk = c.bk;
+  int32_t nbatch = c.nbatch;
+  void *scan_args[] = {&bn, &bk, &nbatch, &tile, &tile_start, &cost_start};
+  hipKernelNodeParams sp = {};
+  sp.func = reinterpret_cast<void *>(&ws_scan_kernel);
+  sp.gridDim = dim3(1);
+  sp.blockDim = dim3(kScanThreads);
+  sp.sharedMemBytes = 0;
+  sp.kernelParams = scan_args;
+  sp.extra = nullptr;
+  BOYS_TRY_HIP(hipGraphAddKernelNode(&scan_node, s.graph, nullptr, 0, &sp));
+
+  WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
+  void *main_args[] = {&args};
+  hipKernelNodeParams mp = {};
+  mp.func = reinterpret_cast<void *>(conf.kernel);
+  mp.gridDim = dim3(unsigned(s.cus * conf.blocks_per_cu));
+  mp.blockDim = dim3(kBlock);
+  mp.sharedMemBytes = 0;
+  mp.kernelParams = main_args;
+  mp.extra = nullptr;
+  BOYS_TRY_HIP(hipGraphAddKernelNode(&main_node, s.graph, &scan_node, 1, &mp));
+
+  BOYS_TRY_HIP(hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0));
+  s.key = key;
+  s.has_key = true;
+  return BOYS_OK;
+}
+
+int validate(const Call &c) {
+  if (c.nbatch < 0 || c.nbatch > kMaxBatches) return BOYS_EINVAL;
+  if (c.nbatch == 0) return BOYS_OK;
+  if (!c.x || !c.boff || !c.bn || !c.bk || !c.w || !c.woff || !c.out) return BOYS_EINVAL;
+  return BOYS_OK;
+}
+
+int device_state(DeviceState **out) {
+  int dev = 0;
+  BOYS_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
+  DeviceState &s = g_dev[dev];
+  if (s.cus == 0) {
+    int cus = 0;
+    BOYS_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    s.cus = cus > 0 ? cus : 1;
+  }
+  *out = &s;
+  return BOYS_OK;
+}
+
+// Enqueues one evaluation with configuration cfg (state lock held).
+int launch(DeviceState &s, const Call &c, int cfg, hipStream_t stream) {
+  if (int st = ensure_workspace(s, c.nbatch)) return st;
+  if (int st = prepare_graph(s, c, cfg)) {
+    drop_graph(s);
+    return st;
+  }
+  BOYS_TRY_HIP(hipGraphLaunch(s.exec, stream));
+  return BOYS_OK;
+}
+
+}  // namespace
+}  // namespace boys
+
+extern "C" {
+
+int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                      const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                      int32_t nbatch, double *out, hipStream_t stream) {
+  using namespace boys;
+  const Call c{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out};
+  if (int st = validate(c)) return st;
+  if (nbatch == 0) return BOYS_OK;
+  if (int st = check_device()) return st;
+  DeviceState *s = nullptr;
+  if (int st = device_state(&s)) return st;
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (s->config < 0) s->config = cached_config(nbatch);
+  return launch(*s, c, s->config, stream);
+}
+
+int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                           const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                           int32_t nbatch, double *out, hipStream_t stream, int *best_config,
+                           float *best_ms) {
+  using namespace boys;
+  const Call c{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out};
+  if (int st = validate(c)) return st;
+  if (nbatch == 0) return BOYS_OK;
+  if (int st = check_device()) return st;
+  DeviceState *s = nullptr;
+  if (int st = device_state(&s)) return st;
+  std::lock_guard<std::mutex> lock(s->mu);
+
+  hipEvent_t e0, e1;
+  BOYS_TRY_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_status(hipGetLastError());
+  }
+  constexpr int kReps = 3;
+  int best = -1;
+  float best_t = 0.0f;
+  int st = BOYS_OK;
+  for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg) {
+    if ((st = launch(*s, c, cfg, stream))) break;  // warm-up (and graph build)
+    float tmin = 0.0f;
+    for (int r = 0; r < kReps && st == BOYS_OK; ++r) {
+      float t = 0.0f;
+      if ((st = hip_status(hipEventRecord(e0, stream)))) break;
+      if ((st = launch(*s, c, cfg, stream))) break;
+      if ((st = hip_status(hipEventRecord(e1, stream)))) break;
+      if ((st = hip_status(hipEventSynchronize(e1)))) break;
+      if ((st = hip_status(hipEventElapsedTime(&t, e0, e1)))) break;
+      if (r == 0 || t < tmin) tmin = t;
+    }
+    if (st == BOYS_OK && (best < 0 || tmin < best_t)) {
+      best = cfg;
+      best_t = tmin;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != BOYS_OK) return st;
+  s->config = best;
+  store_config(nbatch, best);
+  if ((st = launch(*s, c, best, stream))) return st;  // leaves the graph of the winner cached
+  if (best_config) *best_config = best;
+  if (best_ms) *best_ms = best_t;
+  return BOYS_OK;
+}
+
+int boys_weighted_sum_num_configs(void) { return boys::kNumConfigs; }
+
+const char *boys_weighted_sum_config_name(int config) {
+  if (config < 0 || config >= boys::kNumConfigs) return "invalid";
+  return boys::kConfigs[config].name;
+}
+
+int boys_weighted_sum_get_config(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= boys::kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(boys::g_dev[dev].mu);
+  const int c = boys::g_dev[dev].config;
+  return c < 0 ? boys::kDefaultConfig : c;
+}
+
+int boys_weighted_sum_set_config(int config) {
+  if (config < -1 || config >= boys::kNumConfigs) return BOYS_EINVAL;
+  int dev = 0;
+  BOYS_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= boys::kMaxDevices) return BOYS_ENOTSUP;
+  std::lock_guard<std::mutex> lock(boys::g_dev[dev].mu);
+  boys::g_dev[dev].config = config;
+  return BOYS_OK;
+}
+
+void boys_finalize(void) {
+  using namespace boys;
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (int d = 0; d < kMaxDevices; ++d) {
+    DeviceState &s = g_dev[d];
+    std::lock_guard<std::mutex> lock(s.mu);
+    if (!s.ws && !s.exec && !s.graph) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    drop_graph(s);
+    if (s.ws) (void)hipFree(s.ws);
+    s.ws = nullptr;
+    s.ws_cap = 0;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+"""boys_backward and the autograd function on the GPU.
+
+The gradient of L = sum_k G_k F_k(x) is checked against the oracle's
+-sum_k G_k F_{k+1}(x) and against a long-double central difference of L with
+h = 1e-6 max(1, x), to 1e-10 relative.  "Relative" is taken against the
+scale S = sum_k |G_k| F_{k+1}(x) of the sum (the sum itself can cancel to
+zero).  Where the method's absolute guarantee, 5e-14 per F_{k+1}, exceeds
+1e-10 S (orders whose F_{k+1} is below about 5e-4 of the others), the bound
+is that guarantee: tol = max(1e-10 S, 5e-14 sum_k |G_k|)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_10059_amd as boys
+from paper_2512_10059_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+REL = 1e-10
+EPS_TOL = 5e-14
+
+
+def gpu_backward(x, G, kmax=None):
+    xt = torch.from_numpy(x).to(DEV)
+    Gt = torch.from_numpy(np.ascontiguousarray(G)).to(DEV)
+    return boys.boys_backward(xt, Gt, kmax).cpu().numpy()
+
+
+def bounds(x, G):
+    K = G.shape[1] - 1
+    F = oracle.boys(x, K + 1)
+    S = (np.abs(G) * F[:, 1:]).sum(1)
+    return S, np.maximum(REL * S, EPS_TOL * np.abs(G).sum(1))
+
+
+def test_gradient_vs_oracle_and_central_difference():
+    x, G = workloads.backward_workload(n=20000, kmax=16, seed=21)
+    x[:5] = [0.0, 1e-9, 11.899848152108484, 28.98933773882074, 1e4]
+    g = gpu_backward(x, G)
+    S, tol = bounds(x, G)
+    ref = oracle.backward(x, G)
+    fd = oracle.central_difference(x, G)
+    e_ref = np.abs(g - ref)
+    e_fd = np.abs(g - fd)
+    assert np.all(e_ref <= tol), f"vs oracle: worst {np.max(e_ref / tol):.3f} of bound"
+    assert np.all(e_fd <= tol + 1e-12 * S), f"vs central difference: worst {np.max(e_fd / tol):.3f}"
+    # Report how much of the sample meets the strict 1e-10 * S bound.
+    strict = np.mean(e_ref <= REL * S)
+    assert strict > 0.99, f"only {strict:.4f} within 1e-10 S"
+
+
+@pytest.mark.parametrize("kmax", [0, 1, 5, 8, 15, 16, 24, 31])
+def test_every_order(kmax):
+    x, G = workloads.backward_workload(n=3000, kmax=kmax, seed=40 + kmax)
+    g = gpu_backward(x, G)
+    S, tol = bounds(x, G)
+    assert np.all(np.abs(g - oracle.backward(x, G)) <= tol)
+
+
+def test_padded_gradient_rows_and_ragged_sizes():
+    for n in (1, 63, 65, 257, 1000):
+        x, Gfull = workloads.backward_workload(n=n, kmax=20, seed=n)
+        G = Gfull[:, :17]
+        xt = torch.from_numpy(x).to(DEV)
+        Gt = torch.from_numpy(Gfull).to(DEV)[:, :17]  # row stride 21
+        g = boys.boys_backward(xt, Gt, 16).cpu().numpy()
+        S, tol = bounds(x, G)
+        assert np.all(np.abs(g - oracle.backward(x, G)) <= tol), n
+
+
+def test_autograd_matches_kernel_and_oracle():
+    x, G = workloads.backward_workload(n=5000, kmax=16, seed=3)
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    Gt = torch.from_numpy(G).to(DEV)
+    F = boys.BoysFunction.apply(xt, 16)
+    loss = (F * Gt).sum()
+    loss.backward()
+    g = xt.grad.cpu().numpy()
+    direct = boys.boys_backward(xt.detach(), Gt, 16).cpu().numpy()
+    assert np.array_equal(g, direct)
+    S, tol = bounds(x, G)
+    assert np.all(np.abs(g - oracle.backward(x, G)) <= tol)
+    Fo = oracle.boys(x, 16)
+    assert np.abs(F.detach().cpu().numpy() - Fo).max() <= EPS_TOL
+
+
+def test_empty_and_invalid():
+    x = torch.empty(0, dtype=torch.float64, device=DEV)
+    G = torch.empty((0, 17), dtype=torch.float64, device=DEV)
+    assert boys.boys_backward(x, G, 16).numel() == 0
+    x = torch.ones(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(boys.BoysError):
+        boys.boys_backward(x, torch.ones((4, 33), dtype=torch.float64, device=DEV), 32)
+    with pytest.raises(boys.BoysError):
+        boys.boys_backward(x, torch.ones((4, 3), dtype=torch.float64, device=DEV), 5)
+
+
+def test_full_differentiation_workload_sampled():
+    """2^24 arguments, kmax=16: forward plus backward at full size, 2^15
+    sampled gradients against the oracle and the central difference."""
+    x, G = workloads.backward_workload()
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    Gt = torch.from_numpy(G).to(DEV)
+    F = boys.BoysFunction.apply(xt, 16)
+    F.backward(Gt)
+    g = xt.grad
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    idx = np.unique(rng.integers(0, x.size, 1 << 15))
+    gs = g[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    S, tol = bounds(x[idx], G[idx])
+    assert np.all(np.abs(gs - oracle.backward(x[idx], G[idx])) <= tol)
+    assert np.all(np.abs(gs - oracle.central_difference(x[idx], G[idx])) <= tol + 1e-12 * S)
+    Fs = F.detach()[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    assert np.abs(Fs - oracle.boys(x[idx], 16)).max() <= EPS_TOL

@@ -1,0 +1,169 @@
+"""boys_weighted_sum on the GPU against the CPU oracle.
+
+Tolerance: the method's guarantee |F_l - F~_l| <= 5e-14 carried through the
+weighted sum, |out - ref| <= 5e-14 * sum_l |w_l|, plus the rounding of the
+(k+1)-term FP64 accumulation, 4 (k+1) 2^-53 sum_l |w_l F_l|."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_10059_amd as boys
+from paper_2512_10059_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+EPS_TOL = 5e-14
+
+
+def to_dev(bt):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return (t(bt.x), t(bt.batch_off), t(bt.batch_n), t(bt.batch_kmax), t(bt.w), t(bt.w_off))
+
+
+def tolerance(bt, batches=None):
+    """Per-argument bound for the batches listed (default: all)."""
+    tol = np.zeros(bt.x.size)
+    idx = range(bt.batch_off.size) if batches is None else batches
+    for b in idx:
+        off, n, k, wo = (int(bt.batch_off[b]), int(bt.batch_n[b]), int(bt.batch_kmax[b]),
+                         int(bt.w_off[b]))
+        if n <= 0:
+            continue
+        wl = bt.w[wo:wo + k + 1]
+        F = oracle.boys(bt.x[off:off + n], k)
+        tol[off:off + n] = EPS_TOL * np.abs(wl).sum() + 4 * (k + 1) * 2.0**-53 * (np.abs(wl) * F).sum(1)
+    return tol
+
+
+def small_batches(seed=0, nbatch=300, with_empty=True):
+    bt = workloads.batched_workload(nbatch=nbatch, seed=seed, mean_size=300.0, sigma=1.2,
+                                    max_size=5000)
+    if with_empty:
+        bt.batch_n[::37] = 0  # empty batches inside the table
+    return bt
+
+
+def check(bt, out, batches=None):
+    ref = oracle.weighted_sum(bt.x, bt.batch_off, bt.batch_n, bt.batch_kmax, bt.w, bt.w_off)
+    tol = tolerance(bt, batches)
+    mask = np.zeros(bt.x.size, bool)
+    for b in (range(bt.batch_off.size) if batches is None else batches):
+        mask[int(bt.batch_off[b]):int(bt.batch_off[b]) + max(int(bt.batch_n[b]), 0)] = True
+    err = np.abs(out - ref)
+    bad = mask & ~(err <= tol)
+    assert not bad.any(), f"{bad.sum()} outside bound; worst excess {np.max((err - tol)[mask]):.3e}"
+    return err[mask].max()
+
+
+def test_small_batches_default_config():
+    bt = small_batches()
+    args = to_dev(bt)
+    out = boys.boys_weighted_sum(*args).cpu().numpy()
+    check(bt, out)
+    # arguments of empty batches are not written (output was zero-filled)
+    for b in range(0, bt.batch_off.size, 37):
+        assert np.all(out[int(bt.batch_off[b]):int(bt.batch_off[b]) + 1] == 0.0) or bt.batch_n[b] != 0
+
+
+@pytest.mark.parametrize("config", range(8))
+def test_every_config_bitwise_equal(config):
+    """Every tile/binning configuration runs the same arithmetic per argument,
+    so the results are bitwise identical across configurations."""
+    bt = small_batches(seed=1)
+    args = to_dev(bt)
+    boys.weighted_sum_set_config(0)
+    ref = boys.boys_weighted_sum(*args).cpu().numpy()
+    boys.weighted_sum_set_config(config)
+    try:
+        out = boys.boys_weighted_sum(*args).cpu().numpy()
+    finally:
+        boys.weighted_sum_set_config(-1)
+    assert np.array_equal(out, ref, equal_nan=True)
+    if config == 0:
+        check(bt, out)
+
+
+def test_orders_and_domain_edges():
+    """Batches of one argument, orders 0 and 32, region boundaries, x = 0,
+    +inf (0), NaN and negative x (NaN)."""
+    X0, X1 = 11.899848152108484, 28.98933773882074
+    xs = np.array([0.0, 1e-300, X0, np.nextafter(X0, 0), X1, np.nextafter(X1, 99), 30.0, 1e6,
+                   np.inf, np.nan, -1.0])
+    m = xs.size
+    nb = 2 * m
+    x = np.concatenate([xs, xs])
+    off = np.arange(nb, dtype=np.int64)
+    n = np.ones(nb, dtype=np.int32)
+    k = np.array([0] * m + [32] * m, dtype=np.int32)
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(m * 1 + m * 33)
+    w_off = np.concatenate([np.arange(m), m + 33 * np.arange(m)]).astype(np.int64)
+    bt = workloads.Batches(x=x, batch_off=off, batch_n=n, batch_kmax=k, w=w, w_off=w_off)
+    out = boys.boys_weighted_sum(*to_dev(bt)).cpu().numpy()
+    finite = np.isfinite(x) & (x >= 0)
+    ok = np.ones(nb, bool)
+    ok[~finite] = False
+    ref = oracle.weighted_sum(x, off, n, k, w, w_off)
+    tol = tolerance(bt)
+    assert np.all(np.abs(out - ref)[ok] <= tol[ok])
+    assert np.all(out[np.isposinf(x)] == 0.0)
+    assert np.all(np.isnan(out[np.isnan(x) | (x < 0)]))
+
+
+def test_graph_reuse_and_in_place_table_change():
+    """The cached graph is reused for identical arguments and reads the batch
+    table on the device, so an in-place change of the orders is honoured."""
+    bt = small_batches(seed=2, with_empty=False)
+    args = list(to_dev(bt))
+    out = torch.zeros_like(args[0])
+    boys.boys_weighted_sum(*args, out=out)
+    a = out.cpu().numpy().copy()
+    boys.boys_weighted_sum(*args, out=out)
+    assert np.array_equal(out.cpu().numpy(), a)
+    newk = np.minimum(bt.batch_kmax, 3).astype(np.int32)
+    args[3].copy_(torch.from_numpy(newk))
+    boys.boys_weighted_sum(*args, out=out)
+    bt.batch_kmax = newk
+    check(bt, out.cpu().numpy())
+
+
+def test_tuner_picks_a_valid_config():
+    bt = small_batches(seed=3)
+    args = to_dev(bt)
+    cfg, ms, name = boys.boys_tune_weighted_sum(*args)
+    assert 0 <= cfg < boys.weighted_sum_num_configs() and ms > 0 and name != "invalid"
+    assert boys.weighted_sum_get_config() == cfg
+    out = boys.boys_weighted_sum(*args).cpu().numpy()
+    check(bt, out)
+    boys.weighted_sum_set_config(-1)
+
+
+def test_invalid_arguments_raise():
+    bt = small_batches(seed=4)
+    args = list(to_dev(bt))
+    with pytest.raises(boys.BoysError):
+        boys.boys_weighted_sum(args[0].float(), *args[1:])
+    with pytest.raises(boys.BoysError):
+        boys.boys_weighted_sum(args[0], args[1][:-1], *args[2:])
+
+
+def test_full_batched_workload_sampled():
+    """The full batched workload (8192 batches, lognormal sizes with mean 4096,
+    orders uniform on 0..32): 400 sampled batches completely and the first
+    argument of every batch against the oracle."""
+    bt = workloads.batched_workload()
+    args = to_dev(bt)
+    out = boys.boys_weighted_sum(*args).cpu().numpy()
+    rng = np.random.default_rng(8)
+    sample = rng.choice(bt.batch_off.size, 400, replace=False)
+    check(bt, out, batches=sample)
+    firsts = bt.batch_off
+    k = bt.batch_kmax
+    F = oracle.boys(bt.x[firsts], 32)
+    ref = np.array([(bt.w[bt.w_off[b]:bt.w_off[b] + k[b] + 1] * F[b, :k[b] + 1]).sum()
+                    for b in range(firsts.size)])
+    tol = np.array([EPS_TOL * np.abs(bt.w[bt.w_off[b]:bt.w_off[b] + k[b] + 1]).sum() * 1.01
+                    for b in range(firsts.size)])
+    assert np.all(np.abs(out[firsts] - ref) <= tol)
