@@ -232,14 +232,14 @@ def cpu_baseline_leg(torch, wo, fp32):
 
 def copy_probe(torch, dev):
     """A plain elementwise copy of known size, for calibrating HBM counters."""
-    n = 1 << 29  # 4 GiB read + 4 GiB written per launch
-    a = torch.ones(n, dtype=torch.float64, device=dev)
+    n = 1 << 29  # 4 GiB in, 4 GiB out per op; torch splits it into two
+    a = torch.ones(n, dtype=torch.float64, device=dev)  # launches of 2^28 doubles
     b = torch.empty_like(a)
     for _ in range(3):
         torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
-                      "launches": 3}))
+    print(json.dumps({"copy_probe_bytes_read_per_op": n * 8, "copy_probe_bytes_written_per_op": n * 8,
+                      "ops": 3}))
 
 
 def main():
