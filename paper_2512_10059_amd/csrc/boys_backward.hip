@@ -9,9 +9,10 @@
 // order kmax+1 instead of reading values saved by the forward pass: x is
 // 8 bytes per argument while the saved rows would be 8*(kmax+1).  G rows are
 // the dominant traffic (8*(kmax+1) bytes per argument); each wave reads its
-// 64 rows as one contiguous stream into an LDS slice whose row stride is
-// padded to an odd number of doubles, so that the per-lane row reads that
-// follow are free of bank conflicts.
+// 64 rows as one contiguous stream (all loads issued before the evaluation,
+// which hides their latency) into an LDS slice whose row stride is padded to
+// an odd number of doubles, so that the per-lane row reads that follow are
+// free of bank conflicts.
 #include <hip/hip_runtime.h>
 
 #include <array>
@@ -40,13 +41,30 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
     const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     const int rows = n - row0 < 64 ? int(n - row0 > 0 ? n - row0 : 0) : 64;
-    // This wave's rows of G, 64 consecutive doubles per load instruction.
-    for (int e = lane; e < rows * C; e += 64) {
-      const int r = e / C, c = e - r * C;
-      slice[r * CP + c] = __builtin_nontemporal_load(g + (row0 + r) * ld + c);
-    }
     double F[C + 1];
-    boys_f64<K + 1>(i < n ? x[i] : 0.0, F);
+    if (rows == 64) {
+      // Full wave: issue all C loads of this wave's 64 rows of G (64
+      // consecutive elements per instruction when the rows are packed)
+      // before the evaluation, so their latency hides behind it.
+      double gv[C];
+#pragma unroll
+      for (int jj = 0; jj < C; ++jj) {
+        const int e = lane + 64 * jj, r = e / C, c = e - r * C;
+        gv[jj] = __builtin_nontemporal_load(g + (row0 + r) * ld + c);
+      }
+      boys_f64<K + 1>(x[i], F);
+#pragma unroll
+      for (int jj = 0; jj < C; ++jj) {
+        const int e = lane + 64 * jj, r = e / C, c = e - r * C;
+        slice[r * CP + c] = gv[jj];
+      }
+    } else {
+      for (int e = lane; e < rows * C; e += 64) {
+        const int r = e / C, c = e - r * C;
+        slice[r * CP + c] = g[(row0 + r) * ld + c];
+      }
+      boys_f64<K + 1>(i < n ? x[i] : 0.0, F);
+    }
     __syncthreads();
     if (i < n) {
       double acc = 0.0;

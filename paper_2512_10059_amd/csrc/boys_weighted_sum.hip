@@ -104,13 +104,56 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
   }
 }
 
-// Per-workgroup walk state, kept by thread 0 and broadcast through LDS.
+// Per-tile state, computed by thread 0 and broadcast through LDS.
 struct TileInfo {
   int64_t first;  // index of the tile's first argument
+  int64_t woff;   // first weight of the tile's batch
   int32_t count;  // arguments in the tile
   int32_t order;  // k_b
+  int32_t reload; // the batch changed: weights must be (re)loaded
   int32_t done;
 };
+
+// The batch-table fields thread 0 needs for batch b (independent loads).
+struct BatchFields {
+  int64_t cost0, tiles, off, woff;
+  int32_t n, k;
+};
+
+__device__ __forceinline__ BatchFields load_batch(const WsArgs &a, int32_t b) {
+  BatchFields f;
+  f.cost0 = a.cost_start[b];
+  f.tiles = a.tile_start[b + 1] - a.tile_start[b];
+  f.off = a.boff[b];
+  f.woff = a.woff[b];
+  f.n = a.bn[b];
+  f.k = clamp_order(a.bk[b]);
+  return f;
+}
+
+// Largest b in [0, nbatch] with cost_start[b] <= lo, searched by one wave:
+// each round probes 64 evenly spaced entries, so 8192 batches take 3 rounds
+// of dependent loads instead of 13.
+__device__ __forceinline__ int32_t wave_search(const int64_t *cost_start, int32_t nbatch,
+                                               int64_t lo, int lane) {
+  int32_t L = 0, H = nbatch;
+  while (H > L) {
+    const int64_t span = H - L;
+    const int32_t pos = L + int32_t((span * (lane + 1) + 63) / 64);
+    const uint64_t m = __ballot(cost_start[pos] <= lo);
+    const int cnt = __popcll(m);  // the probes that pass form a prefix of the lanes
+    const int32_t p_first = L + int32_t((span + 63) / 64);
+    if (cnt == 0) {
+      H = p_first - 1;
+    } else {
+      const int32_t p_last = L + int32_t((span * cnt + 63) / 64);
+      const int32_t p_next = cnt < 64 ? L + int32_t((span * (cnt + 1) + 63) / 64) - 1 : H;
+      L = p_last;
+      H = p_next;
+    }
+  }
+  return L;
+}
 
 template <int ITEMS, bool BIN>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
@@ -124,61 +167,44 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
 
-  // Thread 0's walk state: batch b, tile j within it.
+  // Walk state of thread 0: batch b, next tile j of it, cost limit hi.
   int32_t b = 0;
-  int64_t j = 0, tiles_b = 0, cs_b = 0, cost_b = 0, hi = 0;
-  int32_t n_b = 0, k_b = 0;
-  int64_t off_b = 0, woff_b = 0;
-  bool load_weights = true;
+  int64_t j = 0, hi = 0;
+  BatchFields f{};
+  bool reload = true;
 
-  if (tid == 0) {
+  if (tid < 64) {
     const int64_t total = a.cost_start[a.nbatch];
     const int64_t lo = total * int64_t(blockIdx.x) / gridDim.x;
-    hi = total * int64_t(blockIdx.x + 1) / gridDim.x;
-    // Largest b with cost_start[b] <= lo.
-    int32_t l = 0, h = a.nbatch;
-    while (l < h) {
-      const int32_t m = (l + h + 1) >> 1;
-      if (a.cost_start[m] <= lo) l = m; else h = m - 1;
-    }
-    b = l;
-    if (b < a.nbatch) {
-      cs_b = a.cost_start[b];
-      tiles_b = a.tile_start[b + 1] - a.tile_start[b];
-      k_b = clamp_order(a.bk[b]);
-      cost_b = k_b + kCostBias;
-      j = (lo - cs_b + cost_b - 1) / cost_b;
+    b = wave_search(a.cost_start, a.nbatch, lo, lane);
+    if (tid == 0) {
+      hi = total * int64_t(blockIdx.x + 1) / gridDim.x;
+      if (b < a.nbatch) {
+        f = load_batch(a, b);
+        const int64_t cost = f.k + kCostBias;
+        j = (lo - f.cost0 + cost - 1) / cost;
+      }
     }
   }
 
   for (;;) {
     if (tid == 0) {
-      // Move past finished and empty batches.
-      while (b < a.nbatch && j >= tiles_b) {
+      while (b < a.nbatch && j >= f.tiles) {  // past this batch: next non-empty one
         ++b;
         j = 0;
-        load_weights = true;
-        if (b < a.nbatch) {
-          cs_b = a.cost_start[b];
-          tiles_b = a.tile_start[b + 1] - a.tile_start[b];
-          k_b = clamp_order(a.bk[b]);
-          cost_b = k_b + kCostBias;
-        }
+        reload = true;
+        if (b < a.nbatch) f = load_batch(a, b);
       }
-      const bool done = b >= a.nbatch || cs_b + j * cost_b >= hi;
+      const bool done = b >= a.nbatch || f.cost0 + j * (f.k + kCostBias) >= hi;
       s_info.done = done;
       if (!done) {
-        if (load_weights) {
-          n_b = a.bn[b];
-          off_b = a.boff[b];
-          woff_b = a.woff[b];
-          for (int l = 0; l <= k_b; ++l) s_w[l] = a.w[woff_b + l];
-          load_weights = false;
-        }
-        s_info.first = off_b + j * T;
-        const int64_t rem = int64_t(n_b) - j * T;
+        s_info.first = f.off + j * T;
+        const int64_t rem = int64_t(f.n) - j * T;
         s_info.count = int32_t(rem < T ? rem : T);
-        s_info.order = k_b;
+        s_info.order = f.k;
+        s_info.woff = f.woff;
+        s_info.reload = reload;
+        reload = false;
       }
       ++j;
     }
@@ -188,6 +214,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     const int64_t first = s_info.first;
     const int count = s_info.count;
     const int k = s_info.order;
+    if (s_info.reload && tid <= k) s_w[tid] = a.w[s_info.woff + tid];
 
     if constexpr (BIN) {
       double xv[ITEMS];
@@ -239,11 +266,18 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         }
       }
     } else {
+      double xv[ITEMS];
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const int p = it * kBlock + tid;
+        xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
+      }
+      __syncthreads();  // weights
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
         const int p = it * kBlock + tid;
         if (p < count) {
-          const double xq = domain(a.x[first + p]);
+          const double xq = xv[it];
           double acc;
           if (xq < kX0) acc = wsum_region_a(xq, k, s_w);
           else if (region_c(xq)) acc = wsum_region_c(xq, k, s_w);

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+argument errors are rejected on the host before any HIP call (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "boys.h")
+LIB = os.path.join(ROOT, "paper_2512_10059_amd", "libboys.so")
+
+EINVAL = -1
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"BOYS_API\s+[\w\s\*]*?\b(boys_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert os.path.exists(LIB), "libboys.so not built"
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ("boys_eval_f64", "boys_eval_f32", "boys_weighted_sum", "boys_backward",
+              "boys_tune_weighted_sum", "boys_strerror", "boys_finalize"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_only_declared_symbols_are_exported():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert exported == declared()
+
+
+def test_strerror(lib):
+    lib.boys_strerror.restype = ctypes.c_char_p
+    assert lib.boys_strerror(0) == b"success"
+    assert b"invalid" in lib.boys_strerror(EINVAL)
+    assert lib.boys_strerror(-99) == b"unknown status"
+
+
+def test_argument_errors_without_gpu(lib):
+    P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    f = lib.boys_eval_f64
+    f.argtypes = [P, I64, I, P, I64, P]
+    dummy = P(4096)
+    assert f(dummy, -1, 8, dummy, 9, None) == EINVAL       # n < 0
+    assert f(dummy, 10, 33, dummy, 34, None) == EINVAL     # kmax > 32
+    assert f(dummy, 10, -1, dummy, 9, None) == EINVAL      # kmax < 0
+    assert f(dummy, 10, 8, dummy, 8, None) == EINVAL       # ld_out < kmax+1
+    assert f(None, 10, 8, dummy, 9, None) == EINVAL        # null x
+    assert f(P(8), 10, 8, P(8), 9, None) == EINVAL         # x overlaps out
+    assert f(dummy, 0, 8, None, 9, None) == 0              # empty: nothing to do
+    g = lib.boys_eval_f32
+    g.argtypes = [P, I64, I, P, I64, P]
+    assert g(dummy, 10, 17, dummy, 18, None) == EINVAL     # FP32 tables stop at 16
+    assert g(dummy, 0, 16, None, 17, None) == 0
+    b = lib.boys_backward
+    b.argtypes = [P, P, I64, I, I64, P, P]
+    assert b(dummy, dummy, 10, 32, 33, dummy, None) == EINVAL  # needs F_{kmax+1}
+    assert b(dummy, dummy, 10, 5, 5, dummy, None) == EINVAL    # ld_g < kmax+1
+    assert b(dummy, dummy, 0, 5, 6, dummy, None) == 0
+    w = lib.boys_weighted_sum
+    w.argtypes = [P] * 6 + [ctypes.c_int32, P, P]
+    assert w(*([dummy] * 6), -1, dummy, None) == EINVAL
+    assert w(*([dummy] * 6), (1 << 24) + 1, dummy, None) == EINVAL
+    assert w(None, *([dummy] * 5), 3, dummy, None) == EINVAL
+    assert w(*([None] * 6), 0, None, None) == 0
+    lib.boys_weighted_sum_set_config.argtypes = [I]
+    assert lib.boys_weighted_sum_set_config(999) == EINVAL
+    assert lib.boys_weighted_sum_num_configs() > 1
