@@ -118,57 +118,74 @@ __device__ __forceinline__ double rational_a_rt(double x, int k) {
   }
 }
 
-// sum_{l=0..k} w[l] F_l(x) on region A: r_{A,k}, then the downward
-// recurrence with the weighted sum accumulated inside it, as in the paper's
-// benchmark consumer (Sec. III, Algorithm 2).  The recurrence enters an
-// unrolled ladder at step k (so every 1/(2l+1) is a literal and every w[l]
-// an LDS read at a constant offset).
-__device__ __forceinline__ double wsum_region_a(double x, int k, const double *w) {
+// Weighted sums for the batched consumer, with the sum accumulated inside the
+// recurrence as in the paper's benchmark consumer (Sec. III, Algorithm 2).
+//
+// The recurrences run in chunks of kChunk steps whose LDS reads (weights,
+// reciprocals) are issued together, so a chunk waits for LDS once rather
+// than once per step.  The tables are padded so that chunks may overrun the
+// order: w[l] = 0 for l < 0 and l > k, which makes the extra steps add
+// exactly zero (their F values stay finite for finite x).  Table layout:
+// w = base + kPad, valid for indices -kPad .. kF64Kmax + kPad.
+constexpr int kChunk = 8;
+constexpr int kPad = kChunk;
+constexpr int kTableLen = kF64Kmax + 1 + 2 * kPad;
+
+// Region A: r_{A,k}, then F_l = (2x F_{l+1} + e^-x) * inv[l] downwards;
+// inv[l] = 1/(2l+1) rounded (finite for the padded l < 0 too).
+__device__ __forceinline__ double wsum_region_a(double x, int k, const double *w,
+                                                const double *inv) {
   const double e = ::exp(-x);
   const double two_x = x + x;
   double F = rational_a_rt(x, k);
   double acc = w[k] * F;
-  switch (k) {
-#define BOYS_DOWN(L)                                          \
-  case L + 1:                                                 \
-    F = __builtin_fma(two_x, F, e) * (1.0 / (2 * (L) + 1));  \
-    acc = __builtin_fma(w[L], F, acc);                        \
-    [[fallthrough]];
-    BOYS_DOWN(31) BOYS_DOWN(30) BOYS_DOWN(29) BOYS_DOWN(28) BOYS_DOWN(27) BOYS_DOWN(26)
-    BOYS_DOWN(25) BOYS_DOWN(24) BOYS_DOWN(23) BOYS_DOWN(22) BOYS_DOWN(21) BOYS_DOWN(20)
-    BOYS_DOWN(19) BOYS_DOWN(18) BOYS_DOWN(17) BOYS_DOWN(16) BOYS_DOWN(15) BOYS_DOWN(14)
-    BOYS_DOWN(13) BOYS_DOWN(12) BOYS_DOWN(11) BOYS_DOWN(10) BOYS_DOWN(9) BOYS_DOWN(8)
-    BOYS_DOWN(7) BOYS_DOWN(6) BOYS_DOWN(5) BOYS_DOWN(4) BOYS_DOWN(3) BOYS_DOWN(2)
-    BOYS_DOWN(1) BOYS_DOWN(0)
-#undef BOYS_DOWN
-    default:
-      break;
+  for (int l0 = k - 1; l0 >= 0; l0 -= kChunk) {
+    double wl[kChunk], il[kChunk];
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) {
+      wl[s] = w[l0 - s];
+      il[s] = inv[l0 - s];
+    }
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) {
+      F = __builtin_fma(two_x, F, e) * il[s];
+      acc = __builtin_fma(wl[s], F, acc);
+    }
   }
   return acc;
 }
 
-// Upward pass with the weighted sum: F_{l+1} = ((2l+1) F_l - e) / (2x),
-// from F_0 = f0; e = e^-x on region B and 0 on region C.
+// Upward pass F_{l+1} = (odd[l] F_l - e) * (1/(2x)), odd[l] = 2l+1, from
+// F_0 = f0; e = e^-x on region B and 0 on region C.
 __device__ __forceinline__ double wsum_upward(double x, double f0, double e, int k,
-                                              const double *w) {
+                                              const double *w, const double *odd) {
   const double inv_2x = 0.5 / x;
   double F = f0;
   double acc = w[0] * F;
+  for (int l0 = 0; l0 < k; l0 += kChunk) {
+    double wl[kChunk], cl[kChunk];
 #pragma unroll
-  for (int l = 0; l < kF64Kmax; ++l) {
-    if (l >= k) break;
-    F = __builtin_fma(double(2 * l + 1), F, -e) * inv_2x;
-    acc = __builtin_fma(w[l + 1], F, acc);
+    for (int s = 0; s < kChunk; ++s) {
+      wl[s] = w[l0 + s + 1];
+      cl[s] = odd[l0 + s];
+    }
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) {
+      F = __builtin_fma(cl[s], F, -e) * inv_2x;
+      acc = __builtin_fma(wl[s], F, acc);
+    }
   }
   return acc;
 }
 
-__device__ __forceinline__ double wsum_region_b(double x, int k, const double *w) {
-  return wsum_upward(x, rational_b(x), ::exp(-x), k, w);
+__device__ __forceinline__ double wsum_region_b(double x, int k, const double *w,
+                                                const double *odd) {
+  return wsum_upward(x, rational_b(x), ::exp(-x), k, w, odd);
 }
 
-__device__ __forceinline__ double wsum_region_c(double x, int k, const double *w) {
-  return wsum_upward(x, kHalfSqrtPi / ::sqrt(x), 0.0, k, w);
+__device__ __forceinline__ double wsum_region_c(double x, int k, const double *w,
+                                                const double *odd) {
+  return wsum_upward(x, kHalfSqrtPi / ::sqrt(x), 0.0, k, w, odd);
 }
 
 }  // namespace boys

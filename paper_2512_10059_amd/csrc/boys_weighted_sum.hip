@@ -59,6 +59,14 @@ struct WsArgs {
 
 __device__ __forceinline__ int clamp_order(int k) { return k < 0 ? 0 : (k > kF64Kmax ? kF64Kmax : k); }
 
+// A value that is identical in every lane, moved to a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Exclusive prefix sums of tiles and cost over the batches (one workgroup).
 __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__restrict__ bn,
                                                                const int32_t *__restrict__ bk,
@@ -158,7 +166,9 @@ __device__ __forceinline__ int32_t wave_search(const int64_t *cost_start, int32_
 template <int ITEMS, bool BIN>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   constexpr int T = kBlock * ITEMS;
-  __shared__ double s_w[kF64Kmax + 1];
+  __shared__ double s_wtab[kTableLen];  // weights of the tile's batch, zero-padded
+  __shared__ double s_inv[kTableLen];   // 1/(2l+1)
+  __shared__ double s_odd[kTableLen];   // 2l+1
   __shared__ double s_x[BIN ? T : 1];
   __shared__ int s_idx[BIN ? T : 1];
   __shared__ int s_count[3], s_fill[3];
@@ -166,6 +176,14 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+
+  double *const s_w = s_wtab + kPad;
+  for (int t = tid; t < kTableLen; t += kBlock) {
+    const int l = t - kPad;
+    s_inv[t] = 1.0 / double(2 * l + 1);
+    s_odd[t] = double(2 * l + 1);
+    s_wtab[t] = 0.0;
+  }
 
   // Walk state of thread 0: batch b, next tile j of it, cost limit hi.
   int32_t b = 0;
@@ -211,10 +229,14 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     if (BIN && tid < 3) s_count[tid] = 0;
     __syncthreads();
     if (s_info.done) break;
-    const int64_t first = s_info.first;
-    const int count = s_info.count;
-    const int k = s_info.order;
-    if (s_info.reload && tid <= k) s_w[tid] = a.w[s_info.woff + tid];
+    // The tile's scalars are the same in every lane; reading them through
+    // readfirstlane puts them in SGPRs, so the order-dependent jumps below
+    // are scalar branches rather than per-lane compares.
+    const int64_t first = uniform(s_info.first);
+    const int count = uniform(s_info.count);
+    const int k = uniform(s_info.order);
+    if (s_info.reload && tid <= kF64Kmax)
+      s_w[tid] = tid <= k ? a.w[uniform(s_info.woff) + tid] : 0.0;
 
     if constexpr (BIN) {
       double xv[ITEMS];
@@ -252,16 +274,16 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
           }
         }
       __syncthreads();
-      const int nA = s_count[0], nAB = s_count[0] + s_count[1];
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
+      const int nA = uniform(s_count[0]), nAB = nA + uniform(s_count[1]);
+#pragma unroll 1
+      for (int it = 0; it < ITEMS; ++it) {  // one copy of the evaluation code
         const int q = it * kBlock + tid;
         if (q < count) {
           const double xq = s_x[q];
           double acc;
-          if (q < nA) acc = wsum_region_a(xq, k, s_w);
-          else if (q < nAB) acc = wsum_region_b(xq, k, s_w);
-          else acc = wsum_region_c(xq, k, s_w);
+          if (q < nA) acc = wsum_region_a(xq, k, s_w, s_inv + kPad);
+          else if (q < nAB) acc = wsum_region_b(xq, k, s_w, s_odd + kPad);
+          else acc = wsum_region_c(xq, k, s_w, s_odd + kPad);
           a.out[first + s_idx[q]] = acc;
         }
       }
@@ -273,15 +295,15 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
       }
       __syncthreads();  // weights
-#pragma unroll
+#pragma unroll 1
       for (int it = 0; it < ITEMS; ++it) {
         const int p = it * kBlock + tid;
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < kX0) acc = wsum_region_a(xq, k, s_w);
-          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_w);
-          else acc = wsum_region_b(xq, k, s_w);
+          if (xq < kX0) acc = wsum_region_a(xq, k, s_w, s_inv + kPad);
+          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_w, s_odd + kPad);
+          else acc = wsum_region_b(xq, k, s_w, s_odd + kPad);
           a.out[first + p] = acc;
         }
       }
