@@ -14,8 +14,9 @@ Beside the headline the same JSON line carries:
   cpu_baseline  the long-double CPU oracle on the first 2^24 arguments
                 (all host cores), with the max abs error of the GPU rows there;
   legs          FP32 vs FP64 at kmax=16 on the same arguments, the batched
-                fused consumer (8192 batches), and the differentiation pass
-                (2^24 arguments, kmax=16, forward + backward).
+                fused consumer (8192 batches), the differentiation pass
+                (2^24 arguments, kmax=16, forward + backward), and the paper's
+                own N^2 benchmark (n = 2^19, k = 12) beside its A100 time.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--only writeout,fp32,fused,backward]
        [--no-cpu-baseline] [--copy-probe]
@@ -200,6 +201,38 @@ def leg_backward(torch, boys, workloads, steps, warmup, dev):
             "gbs_backward": n * 8 * (kmax + 3) / (bms * 1e6)}
 
 
+def leg_pairsum(torch, boys, workloads, steps, dev):
+    """The paper's own benchmark configuration (Sec. III, Algorithm 2): n = 2^19
+    arguments, k = 12, n^2 = 2^38 evaluations.  The paper reports 72 s for it
+    on an NVIDIA A100 (OpenACC); quoted as context, not as a target."""
+    n, kmax = 1 << 19, 12
+    xh, yh, c = workloads.pair_workload(n=n, kmax=kmax)
+    x = torch.from_numpy(xh).to(dev)
+    y = torch.from_numpy(yh).to(dev)
+    z = torch.empty_like(x)
+    boys.boys_pairsum(x, y, c, out=z)  # warm-up (workspace, sort)
+    reps = max(1, min(steps, 3))
+    with Timer(torch) as t:
+        for _ in range(reps):
+            boys.boys_pairsum(x, y, c, out=z)
+    s = t.ms / reps / 1e3
+    pairs = float(n) * n
+    # Region mix of x_i + x_j with x uniform on [0, 30] (triangular density).
+    X0, X1 = 11.899848152108484, 28.98933773882074
+    pa = X0 * X0 / 1800.0
+    pc = 1.0 - X1 * X1 / 1800.0
+    pb = 1.0 - pa - pc
+    from paper_2512_10059_amd.tables import f64_region_a_degrees
+    nm = sum(f64_region_a_degrees()[kmax])
+    flops_pair = pa * (2 * nm + 2 + 3 * kmax) + pb * (25 + 3 * kmax) + pc * (2 + 2 * kmax) + 2 * (kmax + 1) + 2
+    log(f"pairsum: {s:.3f} s per call (paper, A100: 72 s)")
+    return {"n": n, "kmax": kmax, "seconds": s, "pairs_per_s": pairs / s,
+            "values_per_s": pairs * (kmax + 1) / s,
+            "algorithmic_tflops": pairs * flops_pair / s / 1e12,
+            "fp64_peak_frac_algorithmic": pairs * flops_pair / s / 1e12 / FP64_PEAK_TFLOPS,
+            "paper_a100_seconds": 72.0, "paper_xeon6338_seconds_at_n2e14": 40.4}
+
+
 def cpu_baseline_leg(torch, wo, fp32):
     """The oracle on the first 2^24 write-out arguments, all host cores; the
     GPU rows of the same arguments are compared with it on the way."""
@@ -247,7 +280,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="writeout,fp32,fused,backward")
+    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -290,6 +323,11 @@ def main():
             extra["backward"] = leg_backward(torch, boys, workloads, args.steps, args.warmup, dev)
         except Exception as e:
             extra["backward"] = {"error": str(e)}
+    if "pairsum" in legs:
+        try:
+            extra["pairsum"] = leg_pairsum(torch, boys, workloads, args.steps, dev)
+        except Exception as e:
+            extra["pairsum"] = {"error": str(e)}
     if wo is None:  # profiling runs of single legs
         print(json.dumps({"legs": extra}))
         return

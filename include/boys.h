@@ -162,6 +162,27 @@ BOYS_API int boys_weighted_sum_set_config(int config);
 BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax, int64_t ld_g,
                   double *grad_x, hipStream_t stream);
 
+/*
+ * The paper's benchmark workload (Sec. III, Algorithm 2), n^2 Boys
+ * evaluations on arguments formed on the fly:
+ *
+ *     z[i] = sum_{l=0..kmax} c[l] sum_{j=0..n-1} F_l(x[i] + x[j]) y[j].
+ *
+ *   x, y, z  device arrays [n] (FP64); z must not overlap x or y.
+ *   c        HOST array of kmax+1 FP64 weights, read during the call.
+ *   n        0 <= n <= 2^31 - 1.   kmax 0..32 (the FP64 tables).
+ * Each z[i] is summed over j in chunks of 512 terms (chunk sums added in
+ * order), so its rounding is about (512 + n/512) ulps of sum_j |y_j w_ij|
+ * on top of the method's 5e-14 sum_l |c_l| per term.  The arguments are
+ * sorted on the device first (rows evaluated in sorted order, results
+ * scattered back), which needs a per-device workspace of about 32 n bytes
+ * plus sort scratch, allocated on first use and grown when n grows.
+ * Errors: BOYS_EINVAL for bad sizes, orders, null or overlapping pointers;
+ * BOYS_ENOMEM if the workspace cannot grow.
+ */
+BOYS_API int boys_pairsum(const double *x, const double *y, int64_t n, const double *c, int kmax,
+                          double *z, hipStream_t stream);
+
 /* Releases the per-device workspaces and cached graphs of every device. */
 BOYS_API void boys_finalize(void);
 

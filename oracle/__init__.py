@@ -16,6 +16,9 @@ quantities the hot path produces:
                           the integral sign).
 * :func:`central_difference`  the same gradient by a long-double central
                           difference of L, independent of the derivative rule.
+* :func:`pairsum`         z_i = sum_l c_l sum_j F_l(x_i + x_j) y_j, the paper's
+                          benchmark quantity (Sec. III, Algorithm 2), for
+                          selected rows i.
 """
 from __future__ import annotations
 
@@ -137,3 +140,24 @@ def central_difference(x, G, rel_step: float = 1e-6, threads: int = 0) -> np.nda
     Lp = (G * Fp).sum(axis=1)
     Lm = (G * Fm).sum(axis=1)
     return ((Lp - Lm) / (2 * h)).astype(np.float64)
+
+
+def pairsum(x, y, c, rows=None, threads: int = 0):
+    """z_i = sum_l c_l sum_j F_l(x_i + x_j) y_j for i in ``rows`` (default all).
+
+    The argument x_i + x_j is formed in float64 (as the GPU forms it), then
+    everything else is long double.  Returns (z, scale) as float64 arrays
+    where scale_i = sum_j |y_j| sum_l |c_l F_l(x_i + x_j)| bounds the
+    magnitude of the summands (for rounding bounds)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64).astype(np.longdouble)
+    c = np.asarray(c, dtype=np.float64).astype(np.longdouble)
+    k = c.size - 1
+    rows = range(x.size) if rows is None else rows
+    z, scale = [], []
+    for i in rows:
+        F = boys_ld(x[int(i)] + x, k, threads)
+        w = (F * c[None, :]).sum(axis=1)
+        z.append((y * w).sum())
+        scale.append((np.abs(y) * (np.abs(F * c[None, :])).sum(axis=1)).sum())
+    return np.array(z, dtype=np.float64), np.array(scale, dtype=np.float64)

@@ -37,6 +37,7 @@ _SIGNATURES = {
     "boys_weighted_sum_get_config": ([], _INT),
     "boys_weighted_sum_set_config": ([_INT], _INT),
     "boys_backward": ([_P, _P, _I64, _INT, _I64, _P, _P], _INT),
+    "boys_pairsum": ([_P, _P, _I64, _P, _INT, _P, _P], _INT),
     "boys_finalize": ([], None),
 }
 
@@ -198,6 +199,28 @@ def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None
     with torch.cuda.device(x.device):
         _check(lib().boys_backward(_ptr(x), _ptr(grad_f), n, kmax, ld, _ptr(out),
                                    _stream(x.device)), "boys_backward")
+    return out
+
+
+def boys_pairsum(x: torch.Tensor, y: torch.Tensor, c, out: torch.Tensor | None = None) -> torch.Tensor:
+    """z_i = sum_l c_l sum_j F_l(x_i + x_j) y_j (the paper's benchmark workload).
+
+    x, y: FP64 vectors on the GPU; c: the kmax+1 weights (host sequence)."""
+    import numpy as np
+    _vector(x, torch.float64, "x")
+    _vector(y, torch.float64, "y")
+    if y.numel() != x.numel() or y.device != x.device:
+        raise BoysError("x and y must have the same length and device")
+    ch = np.ascontiguousarray(np.asarray(c.cpu() if isinstance(c, torch.Tensor) else c, dtype=np.float64))
+    kmax = ch.size - 1
+    if not 0 <= kmax <= F64_KMAX:
+        raise BoysError(f"c must hold 1..{F64_KMAX + 1} weights")
+    if out is None:
+        out = torch.empty_like(x)
+    _vector(out, torch.float64, "out")
+    with torch.cuda.device(x.device):
+        _check(lib().boys_pairsum(_ptr(x), _ptr(y), x.numel(), _P(ch.ctypes.data), kmax, _ptr(out),
+                                  _stream(x.device)), "boys_pairsum")
     return out
 
 

@@ -18,6 +18,9 @@ int hip_status(hipError_t err);
 // (cached per device), BOYS_EHIP if the device cannot be queried.
 int check_device();
 
+// Frees the workspaces of boys_pairsum on every device (boys_finalize).
+void pairsum_release_all();
+
 // True when [a, a+abytes) and [b, b+bbytes) overlap.
 inline bool overlaps(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
   const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);

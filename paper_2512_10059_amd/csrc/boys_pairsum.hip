@@ -1,0 +1,220 @@
+// boys_pairsum: the paper's benchmark workload (Sec. III, Algorithm 2) on gfx950:
+//
+//     z_i = sum_{l=0..k} c_l sum_j F_l(x_i + x_j) y_j ,   i, j = 0..n-1,
+//
+// i.e. n^2 Boys evaluations formed on the fly, with the weighted sum
+// accumulated inside the recurrence.  The work is VALU-bound (no per-pair
+// memory traffic).
+//
+// Divergence control: the arguments are first sorted (rocPRIM radix sort of
+// (x, index) pairs), so the 64 rows of a wave hold nearly equal x_i and, for
+// a given j, x_i + x_j falls in one region for the whole wave except within
+// a sliver around the region boundaries.  Rows are evaluated in sorted order
+// and the results scattered back.  Each thread owns one row i; the j loop
+// runs over chunks staged in LDS (x_j, y_j read by all lanes at once) and
+// sums every chunk separately before adding it to the row total, which keeps
+// the accumulated rounding at (chunk + n/chunk) ulps instead of n.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <utility>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "boys.h"
+#include "boys_common.hpp"
+#include "boys_device_f64.hpp"
+
+namespace boys {
+namespace {
+
+constexpr int kPairChunk = 512;
+
+struct PairWeights {
+  double c[kF64Kmax + 1];
+};
+
+// sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region.
+template <int K>
+__device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw) {
+  double acc;
+  if (x < kX0) {
+    const double e = ::exp(-x);
+    const double two_x = x + x;
+    double F = rational_a<K>(x);
+    acc = cw.c[K] * F;
+#pragma unroll
+    for (int l = K - 1; l >= 0; --l) {
+      F = __builtin_fma(two_x, F, e) * (1.0 / (2 * l + 1));
+      acc = __builtin_fma(cw.c[l], F, acc);
+    }
+  } else {
+    const bool c = region_c(x);
+    double F, e;
+    if (c) {
+      F = kHalfSqrtPi / ::sqrt(x);
+      e = 0.0;
+    } else {  // region B (and NaN)
+      F = rational_b(x);
+      e = ::exp(-x);
+    }
+    const double inv_2x = 0.5 / x;
+    acc = cw.c[0] * F;
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      F = __builtin_fma(double(2 * l + 1), F, -e) * inv_2x;
+      acc = __builtin_fma(cw.c[l + 1], F, acc);
+    }
+  }
+  return acc;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
+                                                         const double *__restrict__ ys, int64_t n,
+                                                         PairWeights cw, double *__restrict__ zs) {
+  __shared__ double s_x[kPairChunk], s_y[kPairChunk];
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const double xi = i < n ? xs[i] : 0.0;
+  double total = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += kPairChunk) {
+    for (int t = threadIdx.x; t < kPairChunk; t += kBlock) {
+      const int64_t j = j0 + t;
+      s_x[t] = j < n ? xs[j] : 0.0;
+      s_y[t] = j < n ? ys[j] : 0.0;
+    }
+    __syncthreads();
+    const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
+    double part = 0.0;
+    for (int t = 0; t < m; ++t)
+      part = __builtin_fma(s_y[t], pair_weighted<K>(domain(xi + s_x[t]), cw), part);
+    total += part;
+    __syncthreads();
+  }
+  if (i < n) zs[i] = total;
+}
+
+__global__ void iota_kernel(int32_t *idx, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) idx[i] = int32_t(i);
+}
+
+__global__ void gather_kernel(const double *__restrict__ y, const int32_t *__restrict__ idx,
+                              double *__restrict__ ys, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) ys[i] = y[idx[i]];
+}
+
+__global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__restrict__ idx,
+                               double *__restrict__ z, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[idx[i]] = zs[i];
+}
+
+using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, double *);
+
+template <std::size_t... K>
+constexpr auto make_table(std::index_sequence<K...>) {
+  return std::array<PairKernel, sizeof...(K)>{{&pairsum_kernel<int(K)>...}};
+}
+constexpr auto kPairTable = make_table(std::make_index_sequence<kF64Kmax + 1>{});
+
+// Per-device workspace: sorted keys, indices, permuted y and z, sort scratch.
+struct PairState {
+  std::mutex mu;
+  void *buf = nullptr;
+  size_t bytes = 0;
+};
+constexpr int kMaxDevices = 64;
+PairState g_pair[kMaxDevices];
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+void pairsum_release_all() {
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (int d = 0; d < kMaxDevices; ++d) {
+    PairState &s = g_pair[d];
+    std::lock_guard<std::mutex> lock(s.mu);
+    if (!s.buf) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(s.buf);
+    s.buf = nullptr;
+    s.bytes = 0;
+  }
+  if (have) (void)hipSetDevice(cur);
+}
+
+}  // namespace boys
+
+extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const double *c, int kmax,
+                            double *z, hipStream_t stream) {
+  using namespace boys;
+  if (n < 0 || n > (int64_t(1) << 31) - 1 || kmax < 0 || kmax > kF64Kmax) return BOYS_EINVAL;
+  if (n == 0) return BOYS_OK;
+  if (!x || !y || !c || !z) return BOYS_EINVAL;
+  if (overlaps(z, n * 8, x, n * 8) || overlaps(z, n * 8, y, n * 8)) return BOYS_EINVAL;
+  if (int st = check_device()) return st;
+  int dev = 0;
+  BOYS_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
+
+  PairWeights cw{};
+  for (int l = 0; l <= kmax; ++l) cw.c[l] = c[l];
+
+  size_t sort_bytes = 0;
+  BOYS_TRY_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, static_cast<const double *>(nullptr),
+                                         static_cast<double *>(nullptr),
+                                         static_cast<const int32_t *>(nullptr),
+                                         static_cast<int32_t *>(nullptr), size_t(n), 0, 64,
+                                         stream));
+  const size_t un = size_t(n);
+  const size_t off_keys = 0;
+  const size_t off_idx_in = off_keys + align256(8 * un);
+  const size_t off_idx = off_idx_in + align256(4 * un);
+  const size_t off_ys = off_idx + align256(4 * un);
+  const size_t off_zs = off_ys + align256(8 * un);
+  const size_t off_tmp = off_zs + align256(8 * un);
+  const size_t need = off_tmp + align256(sort_bytes);
+
+  PairState &s = g_pair[dev];
+  std::lock_guard<std::mutex> lock(s.mu);
+  if (s.bytes < need) {
+    if (s.buf) {
+      BOYS_TRY_HIP(hipDeviceSynchronize());
+      BOYS_TRY_HIP(hipFree(s.buf));
+      s.buf = nullptr;
+      s.bytes = 0;
+    }
+    if (hipMalloc(&s.buf, need) != hipSuccess) {
+      (void)hipGetLastError();
+      s.buf = nullptr;
+      return BOYS_ENOMEM;
+    }
+    s.bytes = need;
+  }
+  char *base = static_cast<char *>(s.buf);
+  double *keys = reinterpret_cast<double *>(base + off_keys);
+  int32_t *idx_in = reinterpret_cast<int32_t *>(base + off_idx_in);
+  int32_t *idx = reinterpret_cast<int32_t *>(base + off_idx);
+  double *ys = reinterpret_cast<double *>(base + off_ys);
+  double *zs = reinterpret_cast<double *>(base + off_zs);
+  void *tmp = base + off_tmp;
+
+  const unsigned g = unsigned((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(iota_kernel, dim3(g), dim3(kBlock), 0, stream, idx_in, n);
+  BOYS_TRY_HIP(hipGetLastError());
+  BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
+  BOYS_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(kPairTable[kmax], dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, zs);
+  BOYS_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
+  return hip_status(hipGetLastError());
+}

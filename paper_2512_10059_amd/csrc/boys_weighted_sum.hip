@@ -626,6 +626,7 @@ void boys_finalize(void) {
     s.ws_cap = 0;
   }
   if (have_cur) (void)hipSetDevice(cur);
+  pairsum_release_all();
 }
 
 }  // extern "C"

@@ -88,3 +88,14 @@ def backward_workload(n: int = N_BACKWARD, kmax: int = 16, seed: int = 5):
     rng = np.random.default_rng(seed + 1000)
     G = rng.standard_normal((n, kmax + 1))
     return x, G
+
+
+def pair_workload(n: int = 1 << 19, kmax: int = 12, seed: int = 6, x_max: float = 30.0):
+    """The paper's benchmark inputs (Sec. III): x uniform on [0, 30], and y and
+    the kmax+1 weights c drawn N(0,1) (the paper leaves their distribution
+    open).  Its GPU run used n = 2^19 and kmax = 12."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, x_max, n)
+    y = rng.standard_normal(n)
+    c = rng.standard_normal(kmax + 1)
+    return x, y, c

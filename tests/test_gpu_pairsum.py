@@ -1,0 +1,89 @@
+"""boys_pairsum (the paper's benchmark quantity, Sec. III Algorithm 2) on the
+GPU against the oracle.
+
+Per row the bound is the method's 5e-14 per F_l carried through both sums,
+5e-14 sum_l |c_l| sum_j |y_j|, plus FP64 rounding: (k+2) ulps of each
+summand inside w_ij, and (512 + n/512 + 2) ulps of sum_j |y_j w_ij| for the
+chunked sum over j."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_10059_amd as boys
+from paper_2512_10059_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+U = 2.0 ** -53
+
+
+def run(x, y, c):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+    z = boys.boys_pairsum(t(x), t(y), c)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+def check(x, y, c, z, rows):
+    ref, scale = oracle.pairsum(x, y, c, rows)
+    k = len(c) - 1
+    n = x.size
+    tol = 5e-14 * np.abs(c).sum() * np.abs(y).sum() + ((k + 2) + 512 + n / 512 + 2) * U * scale
+    err = np.abs(z[rows] - ref)
+    assert np.all(err <= tol), f"worst {np.max(err / tol):.3f} of the bound"
+    return float(np.max(err / np.maximum(np.abs(ref), 1e-300)))
+
+
+def test_paper_distribution_all_rows():
+    x, y, c = workloads.pair_workload(n=1000, kmax=12, seed=1)
+    z = run(x, y, c)
+    check(x, y, c, z, np.arange(x.size))
+
+
+@pytest.mark.parametrize("kmax", [0, 1, 5, 20, 32])
+def test_orders(kmax):
+    x, y, c = workloads.pair_workload(n=600, kmax=kmax, seed=10 + kmax, x_max=40.0)
+    check(x, y, c, run(x, y, c), np.arange(0, 600, 3))
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 257, 511, 512, 513, 1100])
+def test_ragged_sizes(n):
+    x, y, c = workloads.pair_workload(n=n, kmax=12, seed=n)
+    check(x, y, c, run(x, y, c), np.arange(n))
+
+
+def test_region_boundaries_and_zero():
+    X0, X1 = 11.899848152108484, 28.98933773882074
+    x = np.array([0.0, X0 / 2, np.nextafter(X0 / 2, 0), X1 / 2, X0, X1, 1e-9, 15.0, 100.0, 3e4])
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(x.size)
+    c = rng.standard_normal(13)
+    check(x, y, c, run(x, y, c), np.arange(x.size))
+
+
+def test_permutation_equivariant_and_deterministic():
+    x, y, c = workloads.pair_workload(n=2000, kmax=12, seed=4)
+    z = run(x, y, c)
+    assert np.array_equal(z, run(x, y, c))
+    p = np.random.default_rng(5).permutation(x.size)
+    assert np.array_equal(run(x[p], y[p], c), z[p])
+
+
+def test_invalid_arguments_raise():
+    x = torch.ones(8, dtype=torch.float64, device=DEV)
+    with pytest.raises(boys.BoysError):
+        boys.boys_pairsum(x, x[:4].contiguous(), [1.0])
+    with pytest.raises(boys.BoysError):
+        boys.boys_pairsum(x, x, np.ones(34))
+
+
+def test_paper_size_sampled_rows():
+    """The paper's GPU configuration: n = 2^19, k = 12 (2^38 evaluations),
+    16 sampled rows against the oracle."""
+    x, y, c = workloads.pair_workload()
+    z = run(x, y, c)
+    rows = np.random.default_rng(6).choice(x.size, 16, replace=False)
+    check(x, y, c, z, rows)
+    assert np.all(np.isfinite(z))
