@@ -91,3 +91,18 @@ def test_weight_matches_definition():
             vals.append(float(np.prod([xv / (n + 0.5) for n in range(l, k)])))
         direct.append(max(vals))
     assert np.allclose(remez.rho_a(k)(x).astype(float), direct, rtol=1e-15)
+
+
+@pytest.mark.parametrize("which,k", [("B", 0), ("A", 26)])
+def test_walsh_walk_reproduces_printed_degrees(which, k):
+    """The degree choice of Sec. II D (first anti-diagonal n+m with an entry
+    meeting 5e-14, smallest error on it), run with this Remez, lands on the
+    degrees the appendix prints: (5,6) for r_B, (7,8) for r_{A,26}."""
+    f = remez.boys_k(0 if which == "B" else k)
+    rho = remez.rho_one if which == "B" else remez.rho_a(k)
+    a, b = (T["x0"], T["x1"]) if which == "B" else (0.0, T["x0"])
+    p, q = T["rb"] if which == "B" else T["ra"][k]
+    printed = (len(p) - 1, len(q) - 1)
+    r = remez.walsh_search(f, rho, a, b, 5e-14, d_min=sum(printed) - 1, d_max=sum(printed),
+                           tol=1e-3, dps=40, max_iter=30)
+    assert (r.n, r.m) == printed
