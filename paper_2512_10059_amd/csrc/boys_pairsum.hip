@@ -51,17 +51,21 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw)
       F = __builtin_fma(two_x, F, e) * (1.0 / (2 * l + 1));
       acc = __builtin_fma(cw.c[l], F, acc);
     }
-  } else {
-    const bool c = region_c(x);
-    double F, e;
-    if (c) {
-      F = kHalfSqrtPi / ::sqrt(x);
-      e = 0.0;
-    } else {  // region B (and NaN)
-      F = rational_b(x);
-      e = ::exp(-x);
+  } else if (region_c(x)) {
+    // 1/sqrt(x) and 1/(2x) from one reciprocal square root r.
+    const double r = ::rsqrt(x);
+    const double inv_2x = 0.5 * r * r;
+    double F = kHalfSqrtPi * r;
+    acc = cw.c[0] * F;
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      F = (double(2 * l + 1) * F) * inv_2x;
+      acc = __builtin_fma(cw.c[l + 1], F, acc);
     }
+  } else {  // region B (and NaN)
+    const double e = ::exp(-x);
     const double inv_2x = 0.5 / x;
+    double F = rational_b(x);
     acc = cw.c[0] * F;
 #pragma unroll
     for (int l = 0; l < K; ++l) {
