@@ -112,17 +112,8 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
   }
 }
 
-// Per-tile state, computed by thread 0 and broadcast through LDS.
-struct TileInfo {
-  int64_t first;  // index of the tile's first argument
-  int64_t woff;   // first weight of the tile's batch
-  int32_t count;  // arguments in the tile
-  int32_t order;  // k_b
-  int32_t reload; // the batch changed: weights must be (re)loaded
-  int32_t done;
-};
-
-// The batch-table fields thread 0 needs for batch b (independent loads).
+// The batch-table fields a wave needs for batch b.  Every lane loads the same
+// addresses (one request each) and the values are moved to SGPRs.
 struct BatchFields {
   int64_t cost0, tiles, off, woff;
   int32_t n, k;
@@ -130,12 +121,12 @@ struct BatchFields {
 
 __device__ __forceinline__ BatchFields load_batch(const WsArgs &a, int32_t b) {
   BatchFields f;
-  f.cost0 = a.cost_start[b];
-  f.tiles = a.tile_start[b + 1] - a.tile_start[b];
-  f.off = a.boff[b];
-  f.woff = a.woff[b];
-  f.n = a.bn[b];
-  f.k = clamp_order(a.bk[b]);
+  f.cost0 = uniform(a.cost_start[b]);
+  f.tiles = uniform(a.tile_start[b + 1] - a.tile_start[b]);
+  f.off = uniform(a.boff[b]);
+  f.woff = uniform(a.woff[b]);
+  f.n = uniform(a.bn[b]);
+  f.k = uniform(clamp_order(a.bk[b]));
   return f;
 }
 
@@ -163,152 +154,136 @@ __device__ __forceinline__ int32_t wave_search(const int64_t *cost_start, int32_
   return L;
 }
 
+// Orders LDS accesses of one wave (the hardware executes a wave's LDS
+// instructions in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Persistent kernel in which every wave is an independent worker: wave gw of
+// W takes the tiles whose cost prefix lies in [gw, gw+1) * total / W.  A tile
+// is 64*ITEMS arguments of one batch.  With BIN the wave sorts its tile by
+// region (ballots and lane prefix counts, no atomics) into its LDS slice, so
+// each 64-lane pass over the sorted tile runs a single region path except at
+// the two region boundaries.  No workgroup barrier follows the set-up.
 template <int ITEMS, bool BIN>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
-  constexpr int T = kBlock * ITEMS;
-  __shared__ double s_wtab[kTableLen];  // weights of the tile's batch, zero-padded
-  __shared__ double s_inv[kTableLen];   // 1/(2l+1)
-  __shared__ double s_odd[kTableLen];   // 2l+1
-  __shared__ double s_x[BIN ? T : 1];
-  __shared__ int s_idx[BIN ? T : 1];
-  __shared__ int s_count[3], s_fill[3];
-  __shared__ TileInfo s_info;
+  constexpr int T = 64 * ITEMS;
+  __shared__ double s_inv[kTableLen];  // 1/(2l+1), l = -kPad..
+  __shared__ double s_odd[kTableLen];  // 2l+1
+  __shared__ double s_wtab[kWavesPerBlock][kTableLen];  // weights, zero-padded
+  __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];
+  __shared__ int s_idx[kWavesPerBlock][BIN ? T : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-
-  double *const s_w = s_wtab + kPad;
+  const int wv = tid >> 6;
   for (int t = tid; t < kTableLen; t += kBlock) {
     const int l = t - kPad;
     s_inv[t] = 1.0 / double(2 * l + 1);
     s_odd[t] = double(2 * l + 1);
-    s_wtab[t] = 0.0;
   }
+  for (int t = tid; t < kWavesPerBlock * kTableLen; t += kBlock) (&s_wtab[0][0])[t] = 0.0;
+  __syncthreads();
+  double *const w = &s_wtab[wv][kPad];
+  const double *const inv = s_inv + kPad;
+  const double *const odd = s_odd + kPad;
 
-  // Walk state of thread 0: batch b, next tile j of it, cost limit hi.
-  int32_t b = 0;
-  int64_t j = 0, hi = 0;
+  const int64_t gw = int64_t(blockIdx.x) * kWavesPerBlock + wv;
+  const int64_t W = int64_t(gridDim.x) * kWavesPerBlock;
+  const int64_t total = uniform(a.cost_start[a.nbatch]);
+  const int64_t lo = total * gw / W;
+  const int64_t hi = total * (gw + 1) / W;
+  int32_t b = uniform(wave_search(a.cost_start, a.nbatch, lo, lane));
   BatchFields f{};
+  int64_t j = 0;
+  if (b < a.nbatch) {
+    f = load_batch(a, b);
+    const int64_t cost = f.k + kCostBias;
+    j = (lo - f.cost0 + cost - 1) / cost;
+  }
   bool reload = true;
 
-  if (tid < 64) {
-    const int64_t total = a.cost_start[a.nbatch];
-    const int64_t lo = total * int64_t(blockIdx.x) / gridDim.x;
-    b = wave_search(a.cost_start, a.nbatch, lo, lane);
-    if (tid == 0) {
-      hi = total * int64_t(blockIdx.x + 1) / gridDim.x;
-      if (b < a.nbatch) {
-        f = load_batch(a, b);
-        const int64_t cost = f.k + kCostBias;
-        j = (lo - f.cost0 + cost - 1) / cost;
-      }
-    }
-  }
-
   for (;;) {
-    if (tid == 0) {
-      while (b < a.nbatch && j >= f.tiles) {  // past this batch: next non-empty one
-        ++b;
-        j = 0;
-        reload = true;
-        if (b < a.nbatch) f = load_batch(a, b);
-      }
-      const bool done = b >= a.nbatch || f.cost0 + j * (f.k + kCostBias) >= hi;
-      s_info.done = done;
-      if (!done) {
-        s_info.first = f.off + j * T;
-        const int64_t rem = int64_t(f.n) - j * T;
-        s_info.count = int32_t(rem < T ? rem : T);
-        s_info.order = f.k;
-        s_info.woff = f.woff;
-        s_info.reload = reload;
-        reload = false;
-      }
-      ++j;
+    while (b < a.nbatch && j >= f.tiles) {  // past this batch: next non-empty one
+      ++b;
+      j = 0;
+      reload = true;
+      if (b < a.nbatch) f = load_batch(a, b);
     }
-    if (BIN && tid < 3) s_count[tid] = 0;
-    __syncthreads();
-    if (s_info.done) break;
-    // The tile's scalars are the same in every lane; reading them through
-    // readfirstlane puts them in SGPRs, so the order-dependent jumps below
-    // are scalar branches rather than per-lane compares.
-    const int64_t first = uniform(s_info.first);
-    const int count = uniform(s_info.count);
-    const int k = uniform(s_info.order);
-    if (s_info.reload && tid <= kF64Kmax)
-      s_w[tid] = tid <= k ? a.w[uniform(s_info.woff) + tid] : 0.0;
-
+    if (b >= a.nbatch || f.cost0 + j * (f.k + kCostBias) >= hi) break;
+    const int64_t first = f.off + j * T;
+    const int64_t rem = int64_t(f.n) - j * T;
+    const int count = int(rem < T ? rem : T);
+    const int k = f.k;
+    ++j;
+    if (reload) {
+      if (lane <= kF64Kmax) w[lane] = lane <= k ? a.w[f.woff + lane] : 0.0;
+      reload = false;
+    }
+    double xv[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int p = it * 64 + lane;
+      xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
+    }
     if constexpr (BIN) {
-      double xv[ITEMS];
       int cls[ITEMS];
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
-        const int p = it * kBlock + tid;
-        xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
+        const int p = it * 64 + lane;
         cls[it] = p >= count ? 3 : (xv[it] < kX0 ? 0 : (region_c(xv[it]) ? 2 : 1));
       }
+      // Class c goes to [start_c, start_c + count_c): running base per class.
+      int base = 0, nA = 0, nAB = 0;
 #pragma unroll
-      for (int it = 0; it < ITEMS; ++it)
+      for (int c = 0; c < 3; ++c) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int it = 0; it < ITEMS; ++it) {
           const uint64_t m = __ballot(cls[it] == c);
-          if (lane == 0 && m) atomicAdd(&s_count[c], __popcll(m));
-        }
-      __syncthreads();
-      if (tid < 3) s_fill[tid] = tid == 0 ? 0 : (tid == 1 ? s_count[0] : s_count[0] + s_count[1]);
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const uint64_t m = __ballot(cls[it] == c);
-          if (!m) continue;
-          int base = 0;
-          if (lane == 0) base = atomicAdd(&s_fill[c], __popcll(m));
-          base = __builtin_amdgcn_readfirstlane(base);
           if (cls[it] == c) {
-            const int below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
-            s_x[base + below] = xv[it];
-            s_idx[base + below] = it * kBlock + tid;
+            const int pos = base + int(__builtin_amdgcn_mbcnt_hi(
+                                       uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
+            s_x[wv][pos] = xv[it];
+            s_idx[wv][pos] = it * 64 + lane;
           }
+          base += __popcll(m);
         }
-      __syncthreads();
-      const int nA = uniform(s_count[0]), nAB = nA + uniform(s_count[1]);
+        if (c == 0) nA = base;
+        if (c == 1) nAB = base;
+      }
+      wave_sync();
 #pragma unroll 1
-      for (int it = 0; it < ITEMS; ++it) {  // one copy of the evaluation code
-        const int q = it * kBlock + tid;
+      for (int it = 0; it < ITEMS; ++it) {
+        const int q = it * 64 + lane;
         if (q < count) {
-          const double xq = s_x[q];
+          const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a(xq, k, s_w, s_inv + kPad);
-          else if (q < nAB) acc = wsum_region_b(xq, k, s_w, s_odd + kPad);
-          else acc = wsum_region_c(xq, k, s_w, s_odd + kPad);
-          a.out[first + s_idx[q]] = acc;
+          if (q < nA) acc = wsum_region_a(xq, k, w, inv);
+          else if (q < nAB) acc = wsum_region_b(xq, k, w, odd);
+          else acc = wsum_region_c(xq, k, w, odd);
+          a.out[first + s_idx[wv][q]] = acc;
         }
       }
+      wave_sync();
     } else {
-      double xv[ITEMS];
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
-        const int p = it * kBlock + tid;
-        xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
-      }
-      __syncthreads();  // weights
+      wave_sync();
 #pragma unroll 1
       for (int it = 0; it < ITEMS; ++it) {
-        const int p = it * kBlock + tid;
+        const int p = it * 64 + lane;
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < kX0) acc = wsum_region_a(xq, k, s_w, s_inv + kPad);
-          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_w, s_odd + kPad);
-          else acc = wsum_region_b(xq, k, s_w, s_odd + kPad);
+          if (xq < kX0) acc = wsum_region_a(xq, k, w, inv);
+          else if (region_c(xq)) acc = wsum_region_c(xq, k, w, odd);
+          else acc = wsum_region_b(xq, k, w, odd);
           a.out[first + p] = acc;
         }
       }
+      wave_sync();
     }
-    __syncthreads();
   }
 }
 
@@ -319,21 +294,21 @@ using WsKernel = void (*)(WsArgs);
 
 struct WsConfig {
   WsKernel kernel;
-  int items;        // arguments per thread per tile (tile = 256 * items)
+  int items;        // arguments per lane per tile (tile = 64 * items)
   int bin;          // region binning in LDS
   int blocks_per_cu;
   const char *name;
 };
 
 const WsConfig kConfigs[] = {
-    {&ws_kernel<1, true>, 1, 1, 8, "tile256-bin-8wg"},
-    {&ws_kernel<2, true>, 2, 1, 4, "tile512-bin-4wg"},
-    {&ws_kernel<2, true>, 2, 1, 8, "tile512-bin-8wg"},
-    {&ws_kernel<4, true>, 4, 1, 4, "tile1024-bin-4wg"},
-    {&ws_kernel<4, true>, 4, 1, 8, "tile1024-bin-8wg"},
-    {&ws_kernel<1, false>, 1, 0, 8, "tile256-nobin-8wg"},
-    {&ws_kernel<2, false>, 2, 0, 8, "tile512-nobin-8wg"},
-    {&ws_kernel<4, false>, 4, 0, 4, "tile1024-nobin-4wg"},
+    {&ws_kernel<2, true>, 2, 1, 8, "wave-tile128-bin-8wg"},
+    {&ws_kernel<4, true>, 4, 1, 4, "wave-tile256-bin-4wg"},
+    {&ws_kernel<4, true>, 4, 1, 8, "wave-tile256-bin-8wg"},
+    {&ws_kernel<8, true>, 8, 1, 4, "wave-tile512-bin-4wg"},
+    {&ws_kernel<8, true>, 8, 1, 8, "wave-tile512-bin-8wg"},
+    {&ws_kernel<4, false>, 4, 0, 8, "wave-tile256-nobin-8wg"},
+    {&ws_kernel<2, false>, 2, 0, 8, "wave-tile128-nobin-8wg"},
+    {&ws_kernel<8, false>, 8, 0, 4, "wave-tile512-nobin-4wg"},
 };
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
 constexpr int kDefaultConfig = 2;
@@ -448,7 +423,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   const WsConfig &conf = kConfigs[cfg];
   int64_t *tile_start = s.ws;
   int64_t *cost_start = s.ws + s.ws_cap;
-  int tile = kBlock * conf.items;
+  int tile = 64 * conf.items;
 
   BOYS_TRY_HIP(hipGraphCreate(&s.graph, 0));
   hipGraphNode_t scan_node, main_node;
