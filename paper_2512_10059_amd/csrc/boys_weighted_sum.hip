@@ -35,7 +35,7 @@
 
 #include "boys.h"
 #include "boys_common.hpp"
-#include "boys_device_f64.hpp"
+#include "boys_device_f64_batched.hpp"
 
 namespace boys {
 namespace {
@@ -234,10 +234,13 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
         const int p = it * 64 + lane;
-        cls[it] = p >= count ? 3 : (xv[it] < kX0 ? 0 : (region_c(xv[it]) ? 2 : 1));
+        cls[it] = p >= count ? 3 : (xv[it] < kX0 ? 0 : (region_c(xv[it]) ? 1 : 2));
       }
-      // Class c goes to [start_c, start_c + count_c): running base per class.
-      int base = 0, nA = 0, nAB = 0;
+      // Classes in the order A, C, B: the two 64-lane passes that straddle a
+      // class boundary then pair the cheap asymptote path with one of the
+      // rational paths instead of both rational paths.  Class c goes to
+      // [start_c, start_c + count_c): running base per class.
+      int base = 0, nA = 0, nAC = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
           base += __popcll(m);
         }
         if (c == 0) nA = base;
-        if (c == 1) nAB = base;
+        if (c == 1) nAC = base;
       }
       wave_sync();
 #pragma unroll 1
@@ -262,8 +265,8 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
           const double xq = s_x[wv][q];
           double acc;
           if (q < nA) acc = wsum_region_a(xq, k, w, inv);
-          else if (q < nAB) acc = wsum_region_b(xq, k, w, odd);
-          else acc = wsum_region_c(xq, k, w, odd);
+          else if (q < nAC) acc = wsum_region_c(xq, k, w, odd);
+          else acc = wsum_region_b(xq, k, w, odd);
           a.out[first + s_idx[wv][q]] = acc;
         }
       }
