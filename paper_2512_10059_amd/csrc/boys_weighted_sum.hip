@@ -7,8 +7,8 @@
 // Work decomposition.  Each batch is cut into tiles of T = 256*ITEMS
 // arguments; a tile has one order, so the recurrence length is uniform over
 // it.  A one-block scan kernel turns the batch table into two prefix sums:
-// tiles and cost, where a tile of batch b costs k_b + kCostBias units (the
-// recurrence plus the per-argument work before it).  The persistent kernel
+// tiles, and cost counted per 64-argument pass (pass_cost below), so partial
+// tiles of small batches are not over-weighted.  The persistent kernel
 // then runs a fixed grid of a few workgroups per CU; workgroup g takes the
 // tiles whose cost prefix falls in [g, g+1) * total / grid, i.e. a contiguous
 // run of tiles of about equal cost, walking the batches in order.  There is no
@@ -40,7 +40,11 @@
 namespace boys {
 namespace {
 
-constexpr int kCostBias = 8;
+// Cost of one 64-argument pass of order k, in units of recurrence steps: the
+// chunked recurrence runs 4*ceil(k/4) steps, and the region work before it
+// (rational, exp, binning, loads and stores) is about 24 steps' worth.
+constexpr int kCostBias = 24;
+__host__ __device__ __forceinline__ int64_t pass_cost(int k) { return 4 * ((k + 3) / 4) + kCostBias; }
 constexpr int kScanThreads = 1024;
 constexpr int32_t kMaxBatches = 1 << 24;
 
@@ -81,9 +85,8 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
   int64_t st = 0, sc = 0;
   for (int64_t b = lo; b < hi; ++b) {
     const int64_t n = bn[b] > 0 ? bn[b] : 0;
-    const int64_t t = (n + tile - 1) / tile;
-    st += t;
-    sc += t * (clamp_order(bk[b]) + kCostBias);
+    st += (n + tile - 1) / tile;
+    sc += (n + 63) / 64 * pass_cost(clamp_order(bk[b]));
   }
   s_t[tid] = st;
   s_c[tid] = sc;
@@ -102,9 +105,8 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
     tile_start[b] = st;
     cost_start[b] = sc;
     const int64_t n = bn[b] > 0 ? bn[b] : 0;
-    const int64_t t = (n + tile - 1) / tile;
-    st += t;
-    sc += t * (clamp_order(bk[b]) + kCostBias);
+    st += (n + tile - 1) / tile;
+    sc += (n + 63) / 64 * pass_cost(clamp_order(bk[b]));
   }
   if (tid == kScanThreads - 1) {
     tile_start[nbatch] = s_t[tid];
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   int64_t j = 0;
   if (b < a.nbatch) {
     f = load_batch(a, b);
-    const int64_t cost = f.k + kCostBias;
+    const int64_t cost = ITEMS * pass_cost(f.k);  // a full tile
     j = (lo - f.cost0 + cost - 1) / cost;
   }
   bool reload = true;
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
       reload = true;
       if (b < a.nbatch) f = load_batch(a, b);
     }
-    if (b >= a.nbatch || f.cost0 + j * (f.k + kCostBias) >= hi) break;
+    if (b >= a.nbatch || f.cost0 + j * ITEMS * pass_cost(f.k) >= hi) break;
     const int64_t first = f.off + j * T;
     const int64_t rem = int64_t(f.n) - j * T;
     const int count = int(rem < T ? rem : T);
