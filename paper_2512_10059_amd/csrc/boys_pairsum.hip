@@ -26,7 +26,7 @@
 
 #include "boys.h"
 #include "boys_common.hpp"
-#include "boys_device_f64.hpp"
+#include "boys_device_f64_batched.hpp"
 
 namespace boys {
 namespace {
@@ -44,7 +44,7 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw)
   if (x < kX0) {
     const double e = ::exp(-x);
     const double two_x = x + x;
-    double F = rational_a<K>(x);
+    double F = rational_a_sc<K>(x);
     acc = cw.c[K] * F;
 #pragma unroll
     for (int l = K - 1; l >= 0; --l) {
@@ -65,7 +65,7 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw)
   } else {  // region B (and NaN)
     const double e = ::exp(-x);
     const double inv_2x = 0.5 / x;
-    double F = rational_b(x);
+    double F = rational_b_sc(x);
     acc = cw.c[0] * F;
 #pragma unroll
     for (int l = 0; l < K; ++l) {

@@ -70,6 +70,9 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
   return int64_t((uint64_t(hi) << 32) | lo);
 }
+__device__ __forceinline__ double uniform(double v) {
+  return __builtin_bit_cast(double, uniform(__builtin_bit_cast(int64_t, v)));
+}
 
 // Exclusive prefix sums of tiles and cost over the batches (one workgroup).
 __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__restrict__ bn,
@@ -173,25 +176,23 @@ __device__ __forceinline__ void wave_sync() {
 template <int ITEMS, bool BIN>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   constexpr int T = 64 * ITEMS;
-  __shared__ double s_inv[kTableLen];  // 1/(2l+1), l = -kPad..
-  __shared__ double s_odd[kTableLen];  // 2l+1
-  __shared__ double s_wtab[kWavesPerBlock][kTableLen];  // weights, zero-padded
+  __shared__ wpair s_down[kWavesPerBlock][kTableLen];  // (w_l, 1/(2l+1))
+  __shared__ wpair s_up[kWavesPerBlock][kTableLen];    // (w_{l+1}, 2l+1)
   __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];
   __shared__ int s_idx[kWavesPerBlock][BIN ? T : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  for (int t = tid; t < kTableLen; t += kBlock) {
+  // Each wave fills its own tables: step constants now, weights per batch.
+  for (int t = lane; t < kTableLen; t += 64) {
     const int l = t - kPad;
-    s_inv[t] = 1.0 / double(2 * l + 1);
-    s_odd[t] = double(2 * l + 1);
+    s_down[wv][t] = wpair{0.0, 1.0 / double(2 * l + 1)};
+    s_up[wv][t] = wpair{0.0, double(2 * l + 1)};
   }
-  for (int t = tid; t < kWavesPerBlock * kTableLen; t += kBlock) (&s_wtab[0][0])[t] = 0.0;
-  __syncthreads();
-  double *const w = &s_wtab[wv][kPad];
-  const double *const inv = s_inv + kPad;
-  const double *const odd = s_odd + kPad;
+  wpair *const down = &s_down[wv][kPad];
+  wpair *const up = &s_up[wv][kPad];
+  double w0 = 0.0, wk = 0.0;  // w_0 and w_k of the current batch
 
   const int64_t gw = int64_t(blockIdx.x) * kWavesPerBlock + wv;
   const int64_t W = int64_t(gridDim.x) * kWavesPerBlock;
@@ -222,7 +223,12 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     const int k = f.k;
     ++j;
     if (reload) {
-      if (lane <= kF64Kmax) w[lane] = lane <= k ? a.w[f.woff + lane] : 0.0;
+      if (lane <= kF64Kmax) {
+        down[lane].x = lane <= k ? a.w[f.woff + lane] : 0.0;
+        up[lane].x = lane + 1 <= k ? a.w[f.woff + lane + 1] : 0.0;
+      }
+      w0 = uniform(a.w[f.woff]);
+      wk = uniform(a.w[f.woff + k]);
       reload = false;
     }
     double xv[ITEMS];
@@ -266,9 +272,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (q < count) {
           const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a(xq, k, w, inv);
-          else if (q < nAC) acc = wsum_region_c(xq, k, w, odd);
-          else acc = wsum_region_b(xq, k, w, odd);
+          if (q < nA) acc = wsum_region_a(xq, k, wk, down);
+          else if (q < nAC) acc = wsum_region_c(xq, k, w0, up);
+          else acc = wsum_region_b(xq, k, w0, up);
           a.out[first + s_idx[wv][q]] = acc;
         }
       }
@@ -281,9 +287,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < kX0) acc = wsum_region_a(xq, k, w, inv);
-          else if (region_c(xq)) acc = wsum_region_c(xq, k, w, odd);
-          else acc = wsum_region_b(xq, k, w, odd);
+          if (xq < kX0) acc = wsum_region_a(xq, k, wk, down);
+          else if (region_c(xq)) acc = wsum_region_c(xq, k, w0, up);
+          else acc = wsum_region_b(xq, k, w0, up);
           a.out[first + p] = acc;
         }
       }
@@ -306,17 +312,17 @@ struct WsConfig {
 };
 
 const WsConfig kConfigs[] = {
-    {&ws_kernel<2, true>, 2, 1, 8, "wave-tile128-bin-8wg"},
-    {&ws_kernel<4, true>, 4, 1, 4, "wave-tile256-bin-4wg"},
     {&ws_kernel<4, true>, 4, 1, 8, "wave-tile256-bin-8wg"},
-    {&ws_kernel<8, true>, 8, 1, 4, "wave-tile512-bin-4wg"},
+    {&ws_kernel<4, true>, 4, 1, 12, "wave-tile256-bin-12wg"},
+    {&ws_kernel<4, true>, 4, 1, 16, "wave-tile256-bin-16wg"},
     {&ws_kernel<8, true>, 8, 1, 8, "wave-tile512-bin-8wg"},
-    {&ws_kernel<4, false>, 4, 0, 8, "wave-tile256-nobin-8wg"},
-    {&ws_kernel<2, false>, 2, 0, 8, "wave-tile128-nobin-8wg"},
-    {&ws_kernel<8, false>, 8, 0, 4, "wave-tile512-nobin-4wg"},
+    {&ws_kernel<8, true>, 8, 1, 12, "wave-tile512-bin-12wg"},
+    {&ws_kernel<2, true>, 2, 1, 12, "wave-tile128-bin-12wg"},
+    {&ws_kernel<4, false>, 4, 0, 12, "wave-tile256-nobin-12wg"},
+    {&ws_kernel<2, false>, 2, 0, 12, "wave-tile128-nobin-12wg"},
 };
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
-constexpr int kDefaultConfig = 2;
+constexpr int kDefaultConfig = 1;
 
 // ---------------------------------------------------------------------------
 // Per-device state: workspace, cached graph, chosen configuration.
