@@ -4,6 +4,7 @@
 #pragma once
 
 #include "boys_device_f64.hpp"
+#include "boys_consumer_tables.h"
 
 namespace boys {
 
@@ -23,6 +24,60 @@ __device__ __forceinline__ double fma_uniform_addend(double a, double b, double 
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
   return r;
 }
+
+// ---------------------------------------------------------------------------
+// e^{-x} for the VALU-bound kernels, table-driven (Tang's method for the
+// exponential, ACM TOMS 15(2), 1989).  With N = -rint(128 x / ln2) and
+// r = x + N ln2/128 (|r| <= ln2/256 plus rounding, ln2/128 carried as
+// kExpLHi + kExpLLo),
+//     e^{-x} = 2^(N >> 7) * 2^((N & 127)/128) * e^{-r},
+// the middle factor from a 128-entry table of correctly rounded 2^(i/128)
+// held in LDS by the calling kernel, and e^{-r} - 1 from its degree-5 Taylor
+// polynomial -(r/120)(r^4 - 5r^3 + 20r^2 - 60r + 120), whose truncation is
+// below 1e-18 relative here.  The result is within about 2^-52 relative
+// (table rounding plus one final rounding), against about 46 VALU
+// instructions of the library routine this takes 16, since the domain needs
+// no overflow, underflow or special-value handling: the callers pass
+// 0 <= x < 2^10 or NaN (NaN propagates through r).
+constexpr int kExpTableLen = 1 << BOYS_EXP_TABLE_BITS;
+constexpr double kExpInvL = BOYS_EXP_INV_L;
+constexpr double kExpLHi = BOYS_EXP_L_HI;
+constexpr double kExpLLo = BOYS_EXP_L_LO;
+static __constant__ const double kExp2Table[kExpTableLen] = BOYS_EXP_TABLE_INIT;
+
+// Copies the table to LDS; the caller synchronises the block before use.
+__device__ __forceinline__ void load_exp_table(double *s_tab) {
+  for (int t = threadIdx.x; t < kExpTableLen; t += blockDim.x) s_tab[t] = kExp2Table[t];
+}
+
+__device__ __forceinline__ double exp_neg(double x, const double *s_tab) {
+  const double nd = __builtin_rint(x * kExpInvL);
+  double r = __builtin_fma(-nd, kExpLHi, x);
+  r = __builtin_fma(-nd, kExpLLo, r);
+  const int N = -int(nd);
+  const double T = s_tab[N & (kExpTableLen - 1)];
+  double v = r - 5.0;
+  v = fma_uniform_addend(v, r, 20.0);
+  v = fma_uniform_addend(v, r, -60.0);
+  v = fma_uniform_addend(v, r, 120.0);
+  const double q = (r * (-1.0 / 120.0)) * v;  // e^{-r} - 1
+  return __builtin_amdgcn_ldexp(__builtin_fma(T, q, T), N >> BOYS_EXP_TABLE_BITS);
+}
+
+// ---------------------------------------------------------------------------
+// Region C in closed form.  The asymptote F_0 = (sqrt(pi)/2) x^(-1/2) and its
+// recurrence F_{l+1} = F_l (l + 1/2)/x give F_l = a_l x^(-l-1/2) with
+// a_l = Gamma(l + 1/2)/2, so a weighted sum over orders is
+//     sum_l w_l F_l = x^(-1/2) * sum_l (w_l a_l) (1/x)^l,
+// a polynomial in 1/x whose coefficients d_l = w_l a_l are formed once per
+// batch or call: Horner takes one fused multiply-add per order instead of
+// two multiplies and one fused multiply-add.  Each Horner partial sum times
+// x^(-1/2) (1/x)^l is a tail sum_{m>=l} w_m F_m, so its rounding stays on the
+// scale of sum_m |w_m| F_m, as in the recurrence.
+constexpr int kAsymOrders = BOYS_ASYM_ORDERS;
+constexpr double kAsymCoefHost[kAsymOrders] = BOYS_ASYM_COEF_INIT;
+static __constant__ const double kAsymCoef[kAsymOrders] = BOYS_ASYM_COEF_INIT;
+static_assert(kAsymOrders == kF64Kmax + 1, "one coefficient per order");
 
 // rational_a<K> and rational_b with the Horner steps above (same arithmetic).
 template <int K>
@@ -84,8 +139,9 @@ constexpr int kPad = kChunk;
 constexpr int kTableLen = kF64Kmax + 1 + 2 * kPad;
 
 // Region A: r_{A,k}, then F_l = (2x F_{l+1} + e^-x) * (1/(2l+1)) downwards.
-__device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down) {
-  const double e = ::exp(-x);
+__device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down,
+                                                const double *s_exp) {
+  const double e = exp_neg(x, s_exp);
   const double two_x = x + x;
   double F = rational_a_rt(x, k);
   double acc = wk * F;
@@ -103,8 +159,9 @@ __device__ __forceinline__ double wsum_region_a(double x, int k, double wk, cons
 }
 
 // Region B: r_B, then F_{l+1} = ((2l+1) F_l - e^-x) / (2x) upwards.
-__device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up) {
-  const double e = ::exp(-x);
+__device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up,
+                                                const double *s_exp) {
+  const double e = exp_neg(x, s_exp);
   const double inv_2x = 0.5 / x;
   double F = rational_b_sc(x);
   double acc = w0 * F;
@@ -121,26 +178,26 @@ __device__ __forceinline__ double wsum_region_b(double x, int k, double w0, cons
   return acc;
 }
 
-// Region C needs 1/sqrt(x) and 1/(2x); both come from one reciprocal square
-// root r (about 11 VALU instructions instead of a square root and two
-// divisions, about 33): F_0 = (sqrt(pi)/2) r and 1/(2x) = r^2/2, each within
-// a few ulps, which the asymptote's own 5e-14 error bound dwarfs.
-__device__ __forceinline__ double wsum_region_c(double x, int k, double w0, const wpair *up) {
+// Region C: x^(-1/2) P(1/x) with P(g) = sum_l d_l g^l, d_l = w_l a_l.  The
+// per-wave table holds d_0..d_32 with zeros above k, 16-byte aligned; Horner
+// starts at k rounded up to a whole chunk, where the zeros above k leave P = 0
+// until d_k.  x^(-1/2) and 1/x come from one reciprocal square root r (1/x =
+// r^2, within a few ulps, which the asymptote's own 5e-14 bound dwarfs).
+constexpr int kAsymTableLen = kAsymOrders + 1;  // even: rows stay 16-byte aligned
+__device__ __forceinline__ double wsum_region_c(double x, int k, const double *asym) {
   const double r = ::rsqrt(x);
-  const double inv_2x = 0.5 * r * r;
-  double F = kHalfSqrtPi * r;
-  double acc = w0 * F;
-  for (int l0 = 0; l0 < k; l0 += kChunk) {
-    wpair t[kChunk];
-#pragma unroll
-    for (int s = 0; s < kChunk; ++s) t[s] = up[l0 + s];
-#pragma unroll
-    for (int s = 0; s < kChunk; ++s) {
-      F = (t[s].y * F) * inv_2x;
-      acc = __builtin_fma(t[s].x, F, acc);
-    }
+  const double g = r * r;
+  const int top = (k + kChunk - 1) & ~(kChunk - 1);
+  double P = asym[top];
+  for (int l0 = top - kChunk; l0 >= 0; l0 -= kChunk) {
+    const wpair d01 = *reinterpret_cast<const wpair *>(&asym[l0]);
+    const wpair d23 = *reinterpret_cast<const wpair *>(&asym[l0 + 2]);
+    P = __builtin_fma(P, g, d23.y);
+    P = __builtin_fma(P, g, d23.x);
+    P = __builtin_fma(P, g, d01.y);
+    P = __builtin_fma(P, g, d01.x);
   }
-  return acc;
+  return P * r;
 }
 
 }  // namespace boys

@@ -39,10 +39,11 @@ struct PairWeights {
 
 // sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region.
 template <int K>
-__device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw) {
+__device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
+                                                const PairWeights &dw, const double *s_exp) {
   double acc;
   if (x < kX0) {
-    const double e = ::exp(-x);
+    const double e = exp_neg(x, s_exp);
     const double two_x = x + x;
     double F = rational_a_sc<K>(x);
     acc = cw.c[K] * F;
@@ -52,18 +53,16 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw)
       acc = __builtin_fma(cw.c[l], F, acc);
     }
   } else if (region_c(x)) {
-    // 1/sqrt(x) and 1/(2x) from one reciprocal square root r.
+    // x^(-1/2) sum_l (c_l a_l) (1/x)^l by Horner in 1/x (F_l = a_l x^(-l-1/2)
+    // beyond x1); x^(-1/2) and 1/x from one reciprocal square root r.
     const double r = ::rsqrt(x);
-    const double inv_2x = 0.5 * r * r;
-    double F = kHalfSqrtPi * r;
-    acc = cw.c[0] * F;
+    const double g = r * r;
+    double P = dw.c[K];
 #pragma unroll
-    for (int l = 0; l < K; ++l) {
-      F = (double(2 * l + 1) * F) * inv_2x;
-      acc = __builtin_fma(cw.c[l + 1], F, acc);
-    }
+    for (int l = K - 1; l >= 0; --l) P = fma_uniform_addend(P, g, dw.c[l]);
+    acc = P * r;
   } else {  // region B (and NaN)
-    const double e = ::exp(-x);
+    const double e = exp_neg(x, s_exp);
     const double inv_2x = 0.5 / x;
     double F = rational_b_sc(x);
     acc = cw.c[0] * F;
@@ -79,8 +78,11 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw)
 template <int K>
 __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
                                                          const double *__restrict__ ys, int64_t n,
-                                                         PairWeights cw, double *__restrict__ zs) {
+                                                         PairWeights cw, PairWeights dw,
+                                                         double *__restrict__ zs) {
   __shared__ double s_x[kPairChunk], s_y[kPairChunk];
+  __shared__ double s_exp[kExpTableLen];
+  load_exp_table(s_exp);  // made visible by the first barrier below
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   double total = 0.0;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
     double part = 0.0;
     for (int t = 0; t < m; ++t)
-      part = __builtin_fma(s_y[t], pair_weighted<K>(domain(xi + s_x[t]), cw), part);
+      part = __builtin_fma(s_y[t], pair_weighted<K>(domain(xi + s_x[t]), cw, dw, s_exp), part);
     total += part;
     __syncthreads();
   }
@@ -118,7 +120,8 @@ __global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__r
   if (i < n) z[idx[i]] = zs[i];
 }
 
-using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, double *);
+using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, PairWeights,
+                            double *);
 
 template <std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
@@ -169,8 +172,11 @@ extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const d
   BOYS_TRY_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
 
-  PairWeights cw{};
-  for (int l = 0; l <= kmax; ++l) cw.c[l] = c[l];
+  PairWeights cw{}, dw{};  // c_l, and c_l a_l for region C
+  for (int l = 0; l <= kmax; ++l) {
+    cw.c[l] = c[l];
+    dw.c[l] = c[l] * kAsymCoefHost[l];
+  }
 
   size_t sort_bytes = 0;
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, static_cast<const double *>(nullptr),
@@ -217,7 +223,7 @@ extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const d
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(kPairTable[kmax], dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, zs);
+  hipLaunchKernelGGL(kPairTable[kmax], dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, dw, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
   return hip_status(hipGetLastError());

@@ -4,22 +4,22 @@
 // it:  out[i] = sum_{l=0..k_b} w_{b,l} F_l(x[i]), the weighted sum the paper's
 // benchmark accumulates inside the recurrence (Sec. III, Algorithm 2).
 //
-// Work decomposition.  Each batch is cut into tiles of T = 256*ITEMS
+// Work decomposition.  Each batch is cut into tiles of T = 64*ITEMS
 // arguments; a tile has one order, so the recurrence length is uniform over
 // it.  A one-block scan kernel turns the batch table into two prefix sums:
 // tiles, and cost counted per 64-argument pass (pass_cost below), so partial
-// tiles of small batches are not over-weighted.  The persistent kernel
-// then runs a fixed grid of a few workgroups per CU; workgroup g takes the
-// tiles whose cost prefix falls in [g, g+1) * total / grid, i.e. a contiguous
-// run of tiles of about equal cost, walking the batches in order.  There is no
-// shared counter, so the result is deterministic and no memory has to be
-// reset between launches.
+// tiles of small batches are not over-weighted.  The main kernel then runs a
+// fixed grid of a few workgroups per CU whose waves work independently:
+// wave w of W takes the tiles whose cost prefix falls in [w, w+1) * total / W,
+// i.e. a contiguous run of tiles of about equal cost, walking the batches in
+// order.  There is no shared counter, so the result is deterministic and no
+// memory has to be reset between launches.
 //
 // Divergence.  Argument streams mix all three regions inside every wave, and
-// Algorithm 1 takes a different path in each.  With binning enabled the tile
-// is first sorted by region in LDS (wave-aggregated LDS atomics), so every
-// wave except at most two runs a single path; results are scattered back to
-// their original positions inside the tile.
+// Algorithm 1 takes a different path in each.  With binning enabled the wave
+// first sorts its tile by region in LDS (ballot and bit-count ranks), so every
+// 64-lane pass except at most two runs a single path; results are scattered
+// back to their original positions inside the tile.
 //
 // The scan and the persistent kernel are launched as one cached hipGraph per
 // device; the graph is rebuilt when any argument or the configuration
@@ -75,45 +75,83 @@ __device__ __forceinline__ double uniform(double v) {
 }
 
 // Exclusive prefix sums of tiles and cost over the batches (one workgroup).
+// The table is taken in rounds of kScanThreads * kScanPer batches; thread t
+// owns kScanPer consecutive batches of a round, loads them all at once (the
+// loop is unrolled, so their latencies overlap) and keeps their counts in
+// registers for the write-back.  Tiles are powers of two (1 << tile_shift
+// arguments), so every count is an add and a shift.  Thread totals are
+// scanned within each wave by lane shuffles and across the waves in LDS.
+constexpr int kScanPer = 8;
 __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__restrict__ bn,
                                                                const int32_t *__restrict__ bk,
-                                                               int32_t nbatch, int tile,
+                                                               int32_t nbatch, int tile_shift,
                                                                int64_t *__restrict__ tile_start,
                                                                int64_t *__restrict__ cost_start) {
-  __shared__ int64_t s_t[kScanThreads], s_c[kScanThreads];
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ int64_t s_t[kWaves], s_c[kWaves];
   const int tid = threadIdx.x;
-  const int64_t chunk = (int64_t(nbatch) + kScanThreads - 1) / kScanThreads;
-  const int64_t lo = tid * chunk;
-  const int64_t hi = lo + chunk < nbatch ? lo + chunk : nbatch;
-  int64_t st = 0, sc = 0;
-  for (int64_t b = lo; b < hi; ++b) {
-    const int64_t n = bn[b] > 0 ? bn[b] : 0;
-    st += (n + tile - 1) / tile;
-    sc += (n + 63) / 64 * pass_cost(clamp_order(bk[b]));
-  }
-  s_t[tid] = st;
-  s_c[tid] = sc;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
-    const int64_t at = tid >= off ? s_t[tid - off] : 0;
-    const int64_t ac = tid >= off ? s_c[tid - off] : 0;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int64_t round_up = (int64_t(1) << tile_shift) - 1;
+  int64_t carry_t = 0, carry_c = 0;  // totals of the earlier rounds
+  for (int32_t base = 0; base < nbatch; base += kScanThreads * kScanPer) {
+    const int32_t first = base + tid * kScanPer;
+    int64_t ct[kScanPer], cc[kScanPer];
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const int32_t b = first + i;
+      const int64_t n = b < nbatch && bn[b] > 0 ? bn[b] : 0;
+      const int k = b < nbatch ? bk[b] : 0;
+      ct[i] = (n + round_up) >> tile_shift;
+      cc[i] = ((n + 63) >> 6) * pass_cost(clamp_order(k));
+    }
+    int64_t st = 0, sc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      st += ct[i];
+      sc += cc[i];
+    }
+    int64_t it = st, ic = sc;  // inclusive scan over the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t ut = __shfl_up(it, off);
+      const int64_t uc = __shfl_up(ic, off);
+      if (lane >= off) {
+        it += ut;
+        ic += uc;
+      }
+    }
+    if (lane == 63) {
+      s_t[wv] = it;
+      s_c[wv] = ic;
+    }
     __syncthreads();
-    s_t[tid] += at;
-    s_c[tid] += ac;
-    __syncthreads();
+    int64_t tot_t = 0, tot_c = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wv) {
+        it += s_t[w];
+        ic += s_c[w];
+      }
+      tot_t += s_t[w];
+      tot_c += s_c[w];
+    }
+    __syncthreads();  // s_t, s_c are rewritten by the next round
+    int64_t rt = carry_t + it - st, rc = carry_c + ic - sc;  // exclusive
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const int32_t b = first + i;
+      if (b < nbatch) {
+        tile_start[b] = rt;
+        cost_start[b] = rc;
+      }
+      rt += ct[i];
+      rc += cc[i];
+    }
+    carry_t += tot_t;
+    carry_c += tot_c;
   }
-  st = s_t[tid] - st;  // exclusive
-  sc = s_c[tid] - sc;
-  for (int64_t b = lo; b < hi; ++b) {
-    tile_start[b] = st;
-    cost_start[b] = sc;
-    const int64_t n = bn[b] > 0 ? bn[b] : 0;
-    st += (n + tile - 1) / tile;
-    sc += (n + 63) / 64 * pass_cost(clamp_order(bk[b]));
-  }
-  if (tid == kScanThreads - 1) {
-    tile_start[nbatch] = s_t[tid];
-    cost_start[nbatch] = s_c[tid];
+  if (tid == 0) {
+    tile_start[nbatch] = carry_t;
+    cost_start[nbatch] = carry_c;
   }
 }
 
@@ -175,21 +213,29 @@ __device__ __forceinline__ void wave_sync() {
 // the two region boundaries.  No workgroup barrier follows the set-up.
 template <int ITEMS, bool BIN>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
+  static_assert((ITEMS & (ITEMS - 1)) == 0, "tiles are powers of two: the scan counts them by shifts");
   constexpr int T = 64 * ITEMS;
   __shared__ wpair s_down[kWavesPerBlock][kTableLen];  // (w_l, 1/(2l+1))
   __shared__ wpair s_up[kWavesPerBlock][kTableLen];    // (w_{l+1}, 2l+1)
   __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];
   __shared__ int s_idx[kWavesPerBlock][BIN ? T : 1];
+  __shared__ double s_exp[kExpTableLen];
+  __shared__ __attribute__((aligned(16))) double s_asym[kWavesPerBlock][kAsymTableLen];  // w_l a_l
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  // The wave index is the same in every lane; saying so keeps the per-wave
+  // cost range, the batch fields and the order k in scalar registers, so
+  // loops over k and the choice of r_A,k branch on scalar conditions.
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   // Each wave fills its own tables: step constants now, weights per batch.
   for (int t = lane; t < kTableLen; t += 64) {
     const int l = t - kPad;
     s_down[wv][t] = wpair{0.0, 1.0 / double(2 * l + 1)};
     s_up[wv][t] = wpair{0.0, double(2 * l + 1)};
   }
+  load_exp_table(s_exp);
+  __syncthreads();  // the only block-wide barrier: waves work independently below
   wpair *const down = &s_down[wv][kPad];
   wpair *const up = &s_up[wv][kPad];
   double w0 = 0.0, wk = 0.0;  // w_0 and w_k of the current batch
@@ -224,8 +270,10 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     ++j;
     if (reload) {
       if (lane <= kF64Kmax) {
-        down[lane].x = lane <= k ? a.w[f.woff + lane] : 0.0;
+        const double wl = lane <= k ? a.w[f.woff + lane] : 0.0;
+        down[lane].x = wl;
         up[lane].x = lane + 1 <= k ? a.w[f.woff + lane + 1] : 0.0;
+        s_asym[wv][lane] = wl * kAsymCoef[lane];
       }
       w0 = uniform(a.w[f.woff]);
       wk = uniform(a.w[f.woff + k]);
@@ -272,9 +320,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (q < count) {
           const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a(xq, k, wk, down);
-          else if (q < nAC) acc = wsum_region_c(xq, k, w0, up);
-          else acc = wsum_region_b(xq, k, w0, up);
+          if (q < nA) acc = wsum_region_a(xq, k, wk, down, s_exp);
+          else if (q < nAC) acc = wsum_region_c(xq, k, s_asym[wv]);
+          else acc = wsum_region_b(xq, k, w0, up, s_exp);
           a.out[first + s_idx[wv][q]] = acc;
         }
       }
@@ -287,9 +335,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < kX0) acc = wsum_region_a(xq, k, wk, down);
-          else if (region_c(xq)) acc = wsum_region_c(xq, k, w0, up);
-          else acc = wsum_region_b(xq, k, w0, up);
+          if (xq < kX0) acc = wsum_region_a(xq, k, wk, down, s_exp);
+          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_asym[wv]);
+          else acc = wsum_region_b(xq, k, w0, up, s_exp);
           a.out[first + p] = acc;
         }
       }
@@ -434,14 +482,14 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   const WsConfig &conf = kConfigs[cfg];
   int64_t *tile_start = s.ws;
   int64_t *cost_start = s.ws + s.ws_cap;
-  int tile = 64 * conf.items;
+  int tile_shift = __builtin_ctz(unsigned(64 * conf.items));  // items is a power of two
 
   BOYS_TRY_HIP(hipGraphCreate(&s.graph, 0));
   hipGraphNode_t scan_node, main_node;
 
   const int32_t *bn = c.bn, *bk = c.bk;
   int32_t nbatch = c.nbatch;
-  void *scan_args[] = {&bn, &bk, &nbatch, &tile, &tile_start, &cost_start};
+  void *scan_args[] = {&bn, &bk, &nbatch, &tile_shift, &tile_start, &cost_start};
   hipKernelNodeParams sp = {};
   sp.func = reinterpret_cast<void *>(&ws_scan_kernel);
   sp.gridDim = dim3(1);

@@ -144,3 +144,17 @@ def test_full_writeout_workload_sampled():
         assert bool((blk[:, 1:] <= blk[:, :-1] + EPS_TOL).all())
     del F
     torch.cuda.empty_cache()
+
+
+def test_side_stream_and_stream_order():
+    """The kernel runs on the caller's current stream and is ordered with
+    the work around it on that stream."""
+    x = workloads.gaussian_pair_arguments(50000, seed=13)
+    ref = oracle.boys(x, 20)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        xt = torch.from_numpy(x).to(DEV, non_blocking=False)
+        F = boys.boys_eval_f64(xt * 1.0, 20)   # consumes a product of the same stream
+        G = F * 2.0                            # and feeds a later op on it
+    s.synchronize()
+    assert_close(G.cpu().numpy() / 2.0, ref, what="side stream")

@@ -167,3 +167,58 @@ def test_full_batched_workload_sampled():
     tol = np.array([EPS_TOL * np.abs(bt.w[bt.w_off[b]:bt.w_off[b] + k[b] + 1]).sum() * 1.01
                     for b in range(firsts.size)])
     assert np.all(np.abs(out[firsts] - ref) <= tol)
+
+
+def test_graph_replays_with_eager_work_between():
+    """The cached graph replayed five times, with unrelated eager work (fills,
+    other library kernels) and synchronisations between the replays: every
+    replay equals the first result bitwise."""
+    bt = small_batches(seed=6)
+    args = to_dev(bt)
+    out = torch.zeros_like(args[0])
+    boys.boys_weighted_sum(*args, out=out)
+    torch.cuda.synchronize()
+    first = out.cpu().numpy().copy()
+    scratch = torch.empty(1 << 20, dtype=torch.float64, device=DEV)
+    for r in range(5):
+        out.fill_(float(r) - 7.0)
+        scratch.uniform_()
+        boys.boys_eval_f64(scratch[:4096].abs() * 40, 12)
+        torch.cuda.synchronize()
+        boys.boys_weighted_sum(*args, out=out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        mask = np.zeros(got.size, bool)
+        for o, n in zip(bt.batch_off, bt.batch_n):
+            mask[int(o):int(o) + max(int(n), 0)] = True
+        assert np.array_equal(got[mask], first[mask]), f"replay {r} differs"
+
+
+def test_side_stream():
+    """Launches go to the caller's current stream: a non-default stream gives
+    the same result."""
+    bt = small_batches(seed=7)
+    args = to_dev(bt)
+    ref = boys.boys_weighted_sum(*args).cpu().numpy()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = boys.boys_weighted_sum(*args)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def test_more_batches_than_one_scan_round():
+    """20011 batches (the cost scan takes the table in rounds of 8192, so
+    this needs three, the last one ragged), sizes 1..60, every argument
+    against the oracle."""
+    rng = np.random.default_rng(11)
+    nb = 20011
+    n = rng.integers(0, 61, nb).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(n[:-1])]).astype(np.int64)
+    k = rng.integers(0, 33, nb).astype(np.int32)
+    w_off = np.concatenate([[0], np.cumsum(k[:-1] + 1)]).astype(np.int64)
+    w = rng.standard_normal(int((k + 1).sum()))
+    x = workloads.gaussian_pair_arguments(int(n.sum()), seed=12)
+    bt = workloads.Batches(x=x, batch_off=off, batch_n=n, batch_kmax=k, w=w, w_off=w_off)
+    out = boys.boys_weighted_sum(*to_dev(bt)).cpu().numpy()
+    check(bt, out)
