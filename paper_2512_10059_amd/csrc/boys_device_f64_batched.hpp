@@ -28,8 +28,8 @@ __device__ __forceinline__ double fma_uniform_addend(double a, double b, double 
 // ---------------------------------------------------------------------------
 // e^{-x} for the VALU-bound kernels, table-driven (Tang's method for the
 // exponential, ACM TOMS 15(2), 1989).  With N = -rint(128 x / ln2) and
-// r = x + N ln2/128 (|r| <= ln2/256 plus rounding, ln2/128 carried as
-// kExpLHi + kExpLLo),
+// r = x + N ln2/128 (|r| <= ln2/256 plus rounding, ln2/128 carried as a
+// two-double sum L_hi + L_lo),
 //     e^{-x} = 2^(N >> 7) * 2^((N & 127)/128) * e^{-r},
 // the middle factor from a 128-entry table of correctly rounded 2^(i/128)
 // held in LDS by the calling kernel, and e^{-r} - 1 from its degree-5 Taylor
@@ -40,9 +40,6 @@ __device__ __forceinline__ double fma_uniform_addend(double a, double b, double 
 // no overflow, underflow or special-value handling: the callers pass
 // 0 <= x < 2^10 or NaN (NaN propagates through r).
 constexpr int kExpTableLen = 1 << BOYS_EXP_TABLE_BITS;
-constexpr double kExpInvL = BOYS_EXP_INV_L;
-constexpr double kExpLHi = BOYS_EXP_L_HI;
-constexpr double kExpLLo = BOYS_EXP_L_LO;
 static __constant__ const double kExp2Table[kExpTableLen] = BOYS_EXP_TABLE_INIT;
 
 // Copies the table to LDS; the caller synchronises the block before use.
@@ -50,18 +47,103 @@ __device__ __forceinline__ void load_exp_table(double *s_tab) {
   for (int t = threadIdx.x; t < kExpTableLen; t += blockDim.x) s_tab[t] = kExp2Table[t];
 }
 
+// ---------------------------------------------------------------------------
+// Constants read with scalar loads.  A 64-bit constant written as a literal
+// costs two scalar moves at every use, and on a SIMD the scalar and vector
+// instructions of a wave share its issue slots; these tables are not const,
+// so the compiler fetches them with wide scalar loads (one per eight
+// doubles) instead.
+//
+// r_{A,k} is stored for fixed-length Horner passes: P with zeros above n_k,
+// Q monic with its leading 1 at m_k and zeros above.  The extra leading steps
+// compute 0*x + 0 = 0, then 0*x + 1 = 1, then 1*x + q_{m-1}, which is the
+// x + q_{m-1} of the exact-length pass rounded once, so the result is the
+// same to the last bit.  Orders k >= kSplitK all have (n, m) <= (8, 9);
+// lower orders take (8, 13).
+constexpr int kPadN = BOYS_RA_NMAX;
+constexpr int kPadM = BOYS_RA_MMAX;
+constexpr int kSplitK = 8;
+constexpr int kHiM = 9;
+
+struct CoefTables {
+  double ra_p[kF64Kmax + 1][kPadN + 1];
+  double ra_q[kF64Kmax + 1][kPadM + 1];
+  double rb_p[BOYS_RB_N + 1];
+  double rb_q[BOYS_RB_M + 1];  // monic: rb_q[m] = 1
+  double exp_c[8];             // 128/ln2, -L_hi, -L_lo, -5, 20, -60, 120, -1/120
+};
+
+constexpr CoefTables make_coef_tables() {
+  CoefTables t{};
+  for (int k = 0; k <= kF64Kmax; ++k) {
+    for (int i = 0; i <= kRaN[k]; ++i) t.ra_p[k][i] = kRaP[k][i];
+    for (int i = 0; i < kRaM[k]; ++i) t.ra_q[k][i] = kRaQ[k][i];
+    t.ra_q[k][kRaM[k]] = 1.0;
+  }
+  for (int i = 0; i <= BOYS_RB_N; ++i) t.rb_p[i] = kRbP[i];
+  for (int i = 0; i < BOYS_RB_M; ++i) t.rb_q[i] = kRbQ[i];
+  t.rb_q[BOYS_RB_M] = 1.0;
+  const double c[8] = {BOYS_EXP_INV_L, -BOYS_EXP_L_HI, -BOYS_EXP_L_LO, -5.0, 20.0, -60.0, 120.0,
+                       -1.0 / 120.0};
+  for (int i = 0; i < 8; ++i) t.exp_c[i] = c[i];
+  return t;
+}
+
+constexpr bool split_holds() {
+  for (int k = kSplitK; k <= kF64Kmax; ++k)
+    if (kRaN[k] > kPadN || kRaM[k] > kHiM) return false;
+  return true;
+}
+static_assert(split_holds(), "orders >= kSplitK must fit the (8, 9) pass");
+
+static __constant__ CoefTables kCoef = make_coef_tables();
+
+// e^{-x} (see above).
 __device__ __forceinline__ double exp_neg(double x, const double *s_tab) {
-  const double nd = __builtin_rint(x * kExpInvL);
-  double r = __builtin_fma(-nd, kExpLHi, x);
-  r = __builtin_fma(-nd, kExpLLo, r);
+  const double *c = kCoef.exp_c;
+  const double nd = __builtin_rint(x * c[0]);
+  double r = __builtin_fma(nd, c[1], x);
+  r = __builtin_fma(nd, c[2], r);
   const int N = -int(nd);
   const double T = s_tab[N & (kExpTableLen - 1)];
-  double v = r - 5.0;
-  v = fma_uniform_addend(v, r, 20.0);
-  v = fma_uniform_addend(v, r, -60.0);
-  v = fma_uniform_addend(v, r, 120.0);
-  const double q = (r * (-1.0 / 120.0)) * v;  // e^{-r} - 1
+  double v = r + c[3];
+  v = fma_uniform_addend(v, r, c[4]);
+  v = fma_uniform_addend(v, r, c[5]);
+  v = fma_uniform_addend(v, r, c[6]);
+  const double q = (r * c[7]) * v;  // e^{-r} - 1
   return __builtin_amdgcn_ldexp(__builtin_fma(T, q, T), N >> BOYS_EXP_TABLE_BITS);
+}
+
+// p(x)/q(x) by Horner passes of NP and NQ steps over P[0..NP], Q[0..NQ].
+template <int NP, int NQ>
+__device__ __forceinline__ double rational_loaded(double x, const double *P, const double *Q) {
+  double p = P[NP];
+#pragma unroll
+  for (int i = NP - 1; i >= 0; --i) p = fma_uniform_addend(p, x, P[i]);
+  double q = Q[NQ];
+#pragma unroll
+  for (int i = NQ - 1; i >= 0; --i) q = fma_uniform_addend(q, x, Q[i]);
+  return p / q;
+}
+
+// r_{A,K}(x) for a compile-time order (exact degrees).
+template <int K>
+__device__ __forceinline__ double rational_a_sc(double x) {
+  return rational_loaded<kRaN[K], kRaM[K]>(x, kCoef.ra_p[K], kCoef.ra_q[K]);
+}
+
+// r_B(x).
+__device__ __forceinline__ double rational_b_sc(double x) {
+  return rational_loaded<BOYS_RB_N, BOYS_RB_M>(x, kCoef.rb_p, kCoef.rb_q);
+}
+
+// r_{A,k}(x) for a wave-uniform k in [0, 32]: one of two fixed-length passes
+// over the padded row of k.
+__device__ __forceinline__ double rational_a_rt(double x, int k) {
+  const double *P = kCoef.ra_p[k];
+  const double *Q = kCoef.ra_q[k];
+  if (k < kSplitK) return rational_loaded<kPadN, kPadM>(x, P, Q);
+  return rational_loaded<kPadN, kHiM>(x, P, Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,48 +160,6 @@ constexpr int kAsymOrders = BOYS_ASYM_ORDERS;
 constexpr double kAsymCoefHost[kAsymOrders] = BOYS_ASYM_COEF_INIT;
 static __constant__ const double kAsymCoef[kAsymOrders] = BOYS_ASYM_COEF_INIT;
 static_assert(kAsymOrders == kF64Kmax + 1, "one coefficient per order");
-
-// rational_a<K> and rational_b with the Horner steps above (same arithmetic).
-template <int K>
-__device__ __forceinline__ double rational_a_sc(double x) {
-  constexpr int n = kRaN[K], m = kRaM[K];
-  double p = kRaP[K][n];
-#pragma unroll
-  for (int i = n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, kRaP[K][i]);
-  double q = x + kRaQ[K][m - 1];
-#pragma unroll
-  for (int i = m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, kRaQ[K][i]);
-  return p / q;
-}
-
-__device__ __forceinline__ double rational_b_sc(double x) {
-  double p = kRbP[BOYS_RB_N];
-#pragma unroll
-  for (int i = BOYS_RB_N - 1; i >= 0; --i) p = fma_uniform_addend(p, x, kRbP[i]);
-  double q = x + kRbQ[BOYS_RB_M - 1];
-#pragma unroll
-  for (int i = BOYS_RB_M - 2; i >= 0; --i) q = fma_uniform_addend(q, x, kRbQ[i]);
-  return p / q;
-}
-
-// r_{A,k}(x) for a wave-uniform k in [0, 32] (a jump on a scalar register).
-__device__ __forceinline__ double rational_a_rt(double x, int k) {
-  switch (k) {
-#define BOYS_RA_CASE(K) \
-  case K:               \
-    return rational_a_sc<K>(x);
-    BOYS_RA_CASE(0) BOYS_RA_CASE(1) BOYS_RA_CASE(2) BOYS_RA_CASE(3) BOYS_RA_CASE(4)
-    BOYS_RA_CASE(5) BOYS_RA_CASE(6) BOYS_RA_CASE(7) BOYS_RA_CASE(8) BOYS_RA_CASE(9)
-    BOYS_RA_CASE(10) BOYS_RA_CASE(11) BOYS_RA_CASE(12) BOYS_RA_CASE(13) BOYS_RA_CASE(14)
-    BOYS_RA_CASE(15) BOYS_RA_CASE(16) BOYS_RA_CASE(17) BOYS_RA_CASE(18) BOYS_RA_CASE(19)
-    BOYS_RA_CASE(20) BOYS_RA_CASE(21) BOYS_RA_CASE(22) BOYS_RA_CASE(23) BOYS_RA_CASE(24)
-    BOYS_RA_CASE(25) BOYS_RA_CASE(26) BOYS_RA_CASE(27) BOYS_RA_CASE(28) BOYS_RA_CASE(29)
-    BOYS_RA_CASE(30) BOYS_RA_CASE(31) BOYS_RA_CASE(32)
-#undef BOYS_RA_CASE
-    default:
-      return __builtin_nan("");
-  }
-}
 
 // Weighted sums for the batched consumer, with the sum accumulated inside the
 // recurrence as in the paper's benchmark consumer (Sec. III, Algorithm 2).

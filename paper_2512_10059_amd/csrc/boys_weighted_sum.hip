@@ -173,6 +173,31 @@ __device__ __forceinline__ BatchFields load_batch(const WsArgs &a, int32_t b) {
   return f;
 }
 
+// Lane l's value of v, in a scalar register pair.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Writes the weights w_0..w_k of a batch into the wave's tables (zeros above
+// k) and returns w_0 and w_k.  The loads use indices clamped to k, so they
+// are unconditional and in flight together.
+__device__ __forceinline__ void load_weights(const double *w, int k, int lane, wpair *down,
+                                             wpair *up, double *asym, double &w0, double &wk) {
+  const double wa = w[lane <= k ? lane : k];
+  const double wb = w[lane + 1 <= k ? lane + 1 : k];
+  if (lane <= kF64Kmax) {
+    const double wl = lane <= k ? wa : 0.0;
+    down[lane].x = wl;
+    up[lane].x = lane + 1 <= k ? wb : 0.0;
+    asym[lane] = wl * kAsymCoef[lane];
+  }
+  w0 = readlane_f64(wa, 0);
+  wk = readlane_f64(wa, k);
+}
+
 // Largest b in [0, nbatch] with cost_start[b] <= lo, searched by one wave:
 // each round probes 64 evenly spaced entries, so 8192 batches take 3 rounds
 // of dependent loads instead of 13.
@@ -269,22 +294,20 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     const int k = f.k;
     ++j;
     if (reload) {
-      if (lane <= kF64Kmax) {
-        const double wl = lane <= k ? a.w[f.woff + lane] : 0.0;
-        down[lane].x = wl;
-        up[lane].x = lane + 1 <= k ? a.w[f.woff + lane + 1] : 0.0;
-        s_asym[wv][lane] = wl * kAsymCoef[lane];
-      }
-      w0 = uniform(a.w[f.woff]);
-      wk = uniform(a.w[f.woff + k]);
+      load_weights(a.w + f.woff, k, lane, down, up, s_asym[wv], w0, wk);
       reload = false;
     }
     double xv[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       const int p = it * 64 + lane;
-      xv[it] = p < count ? domain(a.x[first + p]) : 0.0;
+      // Unconditional load from an index clamped into the tile (count >= 1),
+      // so the ITEMS loads are in flight together; lanes past the end are
+      // never evaluated or stored.
+      xv[it] = a.x[first + (p < count ? p : count - 1)];
     }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) xv[it] = domain(xv[it]);
     if constexpr (BIN) {
       int cls[ITEMS];
 #pragma unroll
@@ -373,7 +396,8 @@ constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
 constexpr int kDefaultConfig = 1;
 
 // ---------------------------------------------------------------------------
-// Per-device state: workspace, cached graph, chosen configuration.
+// Per-device state: workspace, one cached graph per configuration (so the
+// tuner can alternate between them without rebuilding), chosen configuration.
 
 struct GraphKey {
   const void *ptrs[7];
@@ -383,27 +407,40 @@ struct GraphKey {
   bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
-struct DeviceState {
-  std::mutex mu;
-  int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
-  int64_t ws_cap = 0;
+struct GraphSlot {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   GraphKey key;
   bool has_key = false;
+};
+
+struct DeviceState {
+  std::mutex mu;
+  int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
+  int64_t ws_cap = 0;
+  GraphSlot slot[kNumConfigs];
   int config = -1;  // -1: not chosen yet
   int cus = 0;
+  bool has_graphs() const {
+    for (const GraphSlot &g : slot)
+      if (g.exec || g.graph) return true;
+    return false;
+  }
 };
 
 constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
 
-void drop_graph(DeviceState &s) {
-  if (s.exec) (void)hipGraphExecDestroy(s.exec);
-  if (s.graph) (void)hipGraphDestroy(s.graph);
-  s.exec = nullptr;
-  s.graph = nullptr;
-  s.has_key = false;
+void drop_slot(GraphSlot &g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+  g.has_key = false;
+}
+
+void drop_graphs(DeviceState &s) {
+  for (GraphSlot &g : s.slot) drop_slot(g);
 }
 
 // Configuration from the tuning cache file named by BOYS_TUNE_CACHE (lines
@@ -455,7 +492,7 @@ int ensure_workspace(DeviceState &s, int32_t nbatch) {
     s.ws = nullptr;
     s.ws_cap = 0;
   }
-  drop_graph(s);
+  drop_graphs(s);
   int64_t cap = 1024;
   while (cap < need) cap *= 2;
   if (hipMalloc(&s.ws, size_t(2 * cap) * sizeof(int64_t)) != hipSuccess) {
@@ -476,15 +513,16 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   key.nbatch = c.nbatch;
   key.config = cfg;
   key.ws = s.ws;
-  if (s.has_key && s.exec && key == s.key) return BOYS_OK;
-  drop_graph(s);
+  GraphSlot &g = s.slot[cfg];
+  if (g.has_key && g.exec && key == g.key) return BOYS_OK;
+  drop_slot(g);
 
   const WsConfig &conf = kConfigs[cfg];
   int64_t *tile_start = s.ws;
   int64_t *cost_start = s.ws + s.ws_cap;
   int tile_shift = __builtin_ctz(unsigned(64 * conf.items));  // items is a power of two
 
-  BOYS_TRY_HIP(hipGraphCreate(&s.graph, 0));
+  BOYS_TRY_HIP(hipGraphCreate(&g.graph, 0));
   hipGraphNode_t scan_node, main_node;
 
   const int32_t *bn = c.bn, *bk = c.bk;
@@ -497,7 +535,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   sp.sharedMemBytes = 0;
   sp.kernelParams = scan_args;
   sp.extra = nullptr;
-  BOYS_TRY_HIP(hipGraphAddKernelNode(&scan_node, s.graph, nullptr, 0, &sp));
+  BOYS_TRY_HIP(hipGraphAddKernelNode(&scan_node, g.graph, nullptr, 0, &sp));
 
   WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
   void *main_args[] = {&args};
@@ -508,11 +546,11 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   mp.sharedMemBytes = 0;
   mp.kernelParams = main_args;
   mp.extra = nullptr;
-  BOYS_TRY_HIP(hipGraphAddKernelNode(&main_node, s.graph, &scan_node, 1, &mp));
+  BOYS_TRY_HIP(hipGraphAddKernelNode(&main_node, g.graph, &scan_node, 1, &mp));
 
-  BOYS_TRY_HIP(hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0));
-  s.key = key;
-  s.has_key = true;
+  BOYS_TRY_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  g.key = key;
+  g.has_key = true;
   return BOYS_OK;
 }
 
@@ -541,10 +579,10 @@ int device_state(DeviceState **out) {
 int launch(DeviceState &s, const Call &c, int cfg, hipStream_t stream) {
   if (int st = ensure_workspace(s, c.nbatch)) return st;
   if (int st = prepare_graph(s, c, cfg)) {
-    drop_graph(s);
+    drop_slot(s.slot[cfg]);
     return st;
   }
-  BOYS_TRY_HIP(hipGraphLaunch(s.exec, stream));
+  BOYS_TRY_HIP(hipGraphLaunch(s.slot[cfg].exec, stream));
   return BOYS_OK;
 }
 
@@ -587,27 +625,29 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
     (void)hipEventDestroy(e0);
     return hip_status(hipGetLastError());
   }
-  constexpr int kReps = 3;
-  int best = -1;
-  float best_t = 0.0f;
+  // Rounds over all configurations, keeping each one's best time: timing
+  // them one after another would favour the first ones, measured while the
+  // clocks are still at their boost level.
+  constexpr int kRounds = 3;
+  float tmin[kNumConfigs] = {};
   int st = BOYS_OK;
-  for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg) {
-    if ((st = launch(*s, c, cfg, stream))) break;  // warm-up (and graph build)
-    float tmin = 0.0f;
-    for (int r = 0; r < kReps && st == BOYS_OK; ++r) {
+  for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg)
+    st = launch(*s, c, cfg, stream);  // warm-up (and graph build)
+  for (int r = 0; r < kRounds && st == BOYS_OK; ++r) {
+    for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg) {
       float t = 0.0f;
       if ((st = hip_status(hipEventRecord(e0, stream)))) break;
       if ((st = launch(*s, c, cfg, stream))) break;
       if ((st = hip_status(hipEventRecord(e1, stream)))) break;
       if ((st = hip_status(hipEventSynchronize(e1)))) break;
       if ((st = hip_status(hipEventElapsedTime(&t, e0, e1)))) break;
-      if (r == 0 || t < tmin) tmin = t;
-    }
-    if (st == BOYS_OK && (best < 0 || tmin < best_t)) {
-      best = cfg;
-      best_t = tmin;
+      if (r == 0 || t < tmin[cfg]) tmin[cfg] = t;
     }
   }
+  int best = 0;
+  for (int cfg = 1; cfg < kNumConfigs; ++cfg)
+    if (tmin[cfg] < tmin[best]) best = cfg;
+  const float best_t = tmin[best];
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != BOYS_OK) return st;
@@ -651,10 +691,10 @@ void boys_finalize(void) {
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState &s = g_dev[d];
     std::lock_guard<std::mutex> lock(s.mu);
-    if (!s.ws && !s.exec && !s.graph) continue;
+    if (!s.ws && !s.has_graphs()) continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     (void)hipDeviceSynchronize();
-    drop_graph(s);
+    drop_graphs(s);
     if (s.ws) (void)hipFree(s.ws);
     s.ws = nullptr;
     s.ws_cap = 0;
