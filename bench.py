@@ -15,10 +15,13 @@ Beside the headline the same JSON line carries:
                 (all host cores), with the max abs error of the GPU rows there;
   legs          FP32 vs FP64 at kmax=16 on the same arguments, the batched
                 fused consumer (8192 batches), the differentiation pass
-                (2^24 arguments, kmax=16, forward + backward), and the paper's
-                own N^2 benchmark (n = 2^19, k = 12) beside its A100 time.
+                (2^24 arguments, kmax=16, forward + backward), the paper's
+                own N^2 benchmark (n = 2^19, k = 12) beside its A100 time, and
+                the screening table set (eps_tol = 1e-10) on the write-out
+                and pair-sum workloads.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--only writeout,fp32,fused,backward]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+       [--only writeout,fp32,fused,backward,pairsum,screen]
        [--no-cpu-baseline] [--copy-probe]
 """
 from __future__ import annotations
@@ -233,7 +236,36 @@ def leg_pairsum(torch, boys, workloads, steps, dev):
             "paper_a100_seconds": 72.0, "paper_xeon6338_seconds_at_n2e14": 40.4}
 
 
-def cpu_baseline_leg(torch, wo, fp32):
+def leg_screen(torch, boys, workloads, steps, warmup, dev, wo=None):
+    """The screening table set (eps_tol = 1e-10): the write-out launch of the
+    headline workload and the pair sums of the paper's benchmark, each timed
+    like its 5e-14 counterpart."""
+    n, kmax, tol = workloads.N_WRITEOUT, 32, 1e-10
+    x = wo["x"] if wo else torch.from_numpy(workloads.gaussian_pair_arguments(n)).to(dev)
+    out = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        boys.boys_eval_f64_tol(x, kmax, tol, out=out)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            boys.boys_eval_f64_tol(x, kmax, tol, out=out)
+    ms = t.ms / steps
+    pn, pk = 1 << 19, 12
+    xh, yh, c = workloads.pair_workload(n=pn, kmax=pk)
+    px, py = torch.from_numpy(xh).to(dev), torch.from_numpy(yh).to(dev)
+    z = torch.empty_like(px)
+    boys.boys_pairsum(px, py, c, out=z, tol=tol)
+    reps = max(1, min(steps, 3))
+    with Timer(torch) as tp:
+        for _ in range(reps):
+            boys.boys_pairsum(px, py, c, out=z, tol=tol)
+    ps = tp.ms / reps / 1e3
+    log(f"screening set: write-out {ms:.3f} ms, pair sums {ps:.3f} s")
+    return {"tol": tol, "writeout_ms": ms, "writeout_values_per_s": n * (kmax + 1) / (ms * 1e-3),
+            "writeout_gbs": n * 8 * (kmax + 2) / (ms * 1e6), "pairsum_seconds": ps,
+            "pairsum_pairs_per_s": float(pn) * pn / ps, "_out": out}
+
+
+def cpu_baseline_leg(torch, wo, fp32, screen=None):
     """The oracle on the first 2^24 write-out arguments, all host cores; the
     GPU rows of the same arguments are compared with it on the way."""
     import oracle
@@ -241,6 +273,7 @@ def cpu_baseline_leg(torch, wo, fp32):
     chunk = 1 << 21
     threads = oracle.max_threads()
     err = 0.0
+    err_screen = 0.0
     t_cpu = 0.0
     for s in range(0, m, chunk):
         xs = wo["x_host"][s:s + chunk]
@@ -249,10 +282,15 @@ def cpu_baseline_leg(torch, wo, fp32):
         t_cpu += time.perf_counter() - t0
         got = wo["out"][s:s + chunk].cpu().numpy()
         err = max(err, float(np.abs(got - ref).max()))
+        if screen is not None:
+            got = screen["_out"][s:s + chunk].cpu().numpy()
+            err_screen = max(err_screen, float(np.abs(got - ref).max()))
     res = {"value": m * 33 / t_cpu, "unit": "values/s", "cores": threads, "kind": "oracle",
            "sample": f"first 2^24 of the 2^26 write-out arguments, kmax=32, long-double oracle, "
                      f"{threads} threads, {t_cpu:.1f} s",
            "gpu_max_abs_err_on_sample": err}
+    if screen is not None:
+        res["screen_max_abs_err_on_sample"] = err_screen
     if fp32 is not None:
         # FP32 path against the FP64 oracle at the FP32-rounded arguments.
         xs = fp32["_x32"][:1 << 20].cpu().numpy().astype(np.float64)
@@ -280,7 +318,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum")
+    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum,screen")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -328,10 +366,17 @@ def main():
             extra["pairsum"] = leg_pairsum(torch, boys, workloads, args.steps, dev)
         except Exception as e:
             extra["pairsum"] = {"error": str(e)}
+    screen = None
+    if "screen" in legs:
+        try:
+            screen = leg_screen(torch, boys, workloads, args.steps, args.warmup, dev, wo)
+            extra["screen"] = {k: v for k, v in screen.items() if not k.startswith("_")}
+        except Exception as e:
+            extra["screen"] = {"error": str(e)}
     if wo is None:  # profiling runs of single legs
         print(json.dumps({"legs": extra}))
         return
-    cpu = None if args.no_cpu_baseline else cpu_baseline_leg(torch, wo, fp32)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_leg(torch, wo, fp32, screen)
 
     ms = wo["ms"]
     achieved = wo["alg_bytes"] / (ms * 1e-3) / 1e9

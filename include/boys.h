@@ -83,6 +83,22 @@ BOYS_API int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, in
                   hipStream_t stream);
 
 /*
+ * boys_eval_f64 at a caller-chosen accuracy (the method at another eps_tol,
+ * Sec. II C-D).  The library holds two table sets and uses the cheaper one
+ * whose guarantee is at most tol:
+ *   tol >= 1e-10   "screening" set: the same x0 (it depends only on kmax),
+ *                  x1 = 23.149988540679747 (the asymptote-error equation at
+ *                  1e-10, root rounded up), r_B and r_{A,k} computed with the
+ *                  library's Remez tool (Walsh-table degree choice, lower
+ *                  degrees than the paper's); |error| <= 1e-10.
+ *   tol >= 5e-14   the paper's tables (identical to boys_eval_f64).
+ * Arguments and layout as boys_eval_f64.  Errors: as boys_eval_f64, and
+ * BOYS_EINVAL for tol < 5e-14 or NaN.
+ */
+BOYS_API int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double tol, double *out,
+                               int64_t ld_out, hipStream_t stream);
+
+/*
  * F_0..F_kmax in FP32 storage (mixed precision; the FP32 variant of
  * Algorithm 1 with the library's own minimax coefficients, regions
  * A' = [0, x0'), B' = [x0', x1'), C' = [x1', inf) for kmax <= 16).
@@ -182,6 +198,15 @@ BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int
  */
 BOYS_API int boys_pairsum(const double *x, const double *y, int64_t n, const double *c, int kmax,
                           double *z, hipStream_t stream);
+
+/*
+ * boys_pairsum with the table set chosen by tol as in boys_eval_f64_tol
+ * (tol >= 1e-10: screening set, per-term bound 1e-10 sum_l |c_l|; tol >=
+ * 5e-14: the paper's).  Errors: as boys_pairsum, and BOYS_EINVAL for
+ * tol < 5e-14 or NaN.
+ */
+BOYS_API int boys_pairsum_tol(const double *x, const double *y, int64_t n, const double *c,
+                              int kmax, double tol, double *z, hipStream_t stream);
 
 /* Releases the per-device workspaces and cached graphs of every device. */
 BOYS_API void boys_finalize(void);

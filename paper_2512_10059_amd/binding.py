@@ -28,6 +28,7 @@ _SIGNATURES = {
     "boys_strerror": ([_INT], ctypes.c_char_p),
     "boys_last_hip_error": ([], _INT),
     "boys_eval_f64": ([_P, _I64, _INT, _P, _I64, _P], _INT),
+    "boys_eval_f64_tol": ([_P, _I64, _INT, ctypes.c_double, _P, _I64, _P], _INT),
     "boys_eval_f32": ([_P, _I64, _INT, _P, _I64, _P], _INT),
     "boys_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P], _INT),
     "boys_tune_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P,
@@ -38,6 +39,7 @@ _SIGNATURES = {
     "boys_weighted_sum_set_config": ([_INT], _INT),
     "boys_backward": ([_P, _P, _I64, _INT, _I64, _P, _P], _INT),
     "boys_pairsum": ([_P, _P, _I64, _P, _INT, _P, _P], _INT),
+    "boys_pairsum_tol": ([_P, _P, _I64, _P, _INT, ctypes.c_double, _P, _P], _INT),
     "boys_finalize": ([], None),
 }
 
@@ -117,6 +119,23 @@ def _eval(name: str, x: torch.Tensor, kmax: int, out, dtype, limit: int):
 def boys_eval_f64(x: torch.Tensor, kmax: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """F_0..F_kmax(x) in FP64 as an (n, kmax+1) tensor (or into ``out``)."""
     return _eval("boys_eval_f64", x, kmax, out, torch.float64, F64_KMAX)
+
+
+def boys_eval_f64_tol(x: torch.Tensor, kmax: int, tol: float,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """boys_eval_f64 with the cheaper table set whose guarantee is at most tol
+    (tol >= 1e-10: the screening set; tol >= 5e-14: the paper's)."""
+    _vector(x, torch.float64, "x")
+    if not 0 <= kmax <= F64_KMAX:
+        raise BoysError(f"kmax must be in [0, {F64_KMAX}]")
+    n = x.numel()
+    if out is None:
+        out = torch.empty((n, kmax + 1), dtype=torch.float64, device=x.device)
+    ld = _rows(out, n, kmax + 1, torch.float64, x.device, "out")
+    with torch.cuda.device(x.device):
+        _check(lib().boys_eval_f64_tol(_ptr(x), n, kmax, float(tol), _ptr(out), ld,
+                                       _stream(x.device)), "boys_eval_f64_tol")
+    return out
 
 
 def boys_eval_f32(x: torch.Tensor, kmax: int, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -202,10 +221,12 @@ def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None
     return out
 
 
-def boys_pairsum(x: torch.Tensor, y: torch.Tensor, c, out: torch.Tensor | None = None) -> torch.Tensor:
+def boys_pairsum(x: torch.Tensor, y: torch.Tensor, c, out: torch.Tensor | None = None,
+                 tol: float | None = None) -> torch.Tensor:
     """z_i = sum_l c_l sum_j F_l(x_i + x_j) y_j (the paper's benchmark workload).
 
-    x, y: FP64 vectors on the GPU; c: the kmax+1 weights (host sequence)."""
+    x, y: FP64 vectors on the GPU; c: the kmax+1 weights (host sequence).
+    tol: None for the paper's tables, else as boys_eval_f64_tol."""
     import numpy as np
     _vector(x, torch.float64, "x")
     _vector(y, torch.float64, "y")
@@ -219,8 +240,13 @@ def boys_pairsum(x: torch.Tensor, y: torch.Tensor, c, out: torch.Tensor | None =
         out = torch.empty_like(x)
     _vector(out, torch.float64, "out")
     with torch.cuda.device(x.device):
-        _check(lib().boys_pairsum(_ptr(x), _ptr(y), x.numel(), _P(ch.ctypes.data), kmax, _ptr(out),
-                                  _stream(x.device)), "boys_pairsum")
+        if tol is None:
+            _check(lib().boys_pairsum(_ptr(x), _ptr(y), x.numel(), _P(ch.ctypes.data), kmax,
+                                      _ptr(out), _stream(x.device)), "boys_pairsum")
+        else:
+            _check(lib().boys_pairsum_tol(_ptr(x), _ptr(y), x.numel(), _P(ch.ctypes.data), kmax,
+                                          float(tol), _ptr(out), _stream(x.device)),
+                   "boys_pairsum_tol")
     return out
 
 

@@ -7,48 +7,92 @@
 #include <hip/hip_runtime.h>
 
 #include "boys_coeffs_f64.h"
+#include "boys_coeffs_f64_screen.h"
 
 namespace boys {
 
 constexpr int kF64Kmax = BOYS_F64_KMAX;
-constexpr double kX0 = BOYS_F64_X0;  // A = [0, x0)
-constexpr double kX1 = BOYS_F64_X1;  // C = (x1, inf), see region_c()
 constexpr double kHalfSqrtPi = 0.88622692545275801364908374167057259;
 
-constexpr int kRaN[kF64Kmax + 1] = BOYS_RA_DEG_N_INIT;
-constexpr int kRaM[kF64Kmax + 1] = BOYS_RA_DEG_M_INIT;
-constexpr double kRaP[kF64Kmax + 1][BOYS_RA_NMAX + 1] = BOYS_RA_P_INIT;
-constexpr double kRaQ[kF64Kmax + 1][BOYS_RA_MMAX + 1] = BOYS_RA_Q_INIT;
-constexpr double kRbP[BOYS_RB_N + 1] = BOYS_RB_P_INIT;
-constexpr double kRbQ[BOYS_RB_M + 1] = BOYS_RB_Q_INIT;
+// A table set of the method: region constants and the coefficients of r_B
+// and r_{A,k}, k = 0..32, from degree 0 upwards with monic denominators
+// (q[m] = 1).  PaperTables are the appendix's (eps_tol = 5e-14, Sec. II F);
+// ScreenTables are the same construction at eps_tol = 1e-10 (same x0, which
+// depends only on kmax; x1 from the asymptote-error equation at 1e-10; the
+// rationals from the Remez tool with the Walsh-table degree choice).
+struct PaperTables {
+  static constexpr double eps = 5e-14;
+  static constexpr double x0 = BOYS_F64_X0;  // A = [0, x0)
+  static constexpr double x1 = BOYS_F64_X1;  // C = (x1, inf), see region_c()
+  static constexpr int rb_n = BOYS_RB_N, rb_m = BOYS_RB_M;
+  static constexpr int ra_n[kF64Kmax + 1] = BOYS_RA_DEG_N_INIT;
+  static constexpr int ra_m[kF64Kmax + 1] = BOYS_RA_DEG_M_INIT;
+  static constexpr double ra_p[kF64Kmax + 1][BOYS_RA_NMAX + 1] = BOYS_RA_P_INIT;
+  static constexpr double ra_q[kF64Kmax + 1][BOYS_RA_MMAX + 1] = BOYS_RA_Q_INIT;
+  static constexpr double rb_p[BOYS_RB_N + 1] = BOYS_RB_P_INIT;
+  static constexpr double rb_q[BOYS_RB_M + 1] = BOYS_RB_Q_INIT;
+};
+
+struct ScreenTables {
+  static constexpr double eps = BOYS_SCR_EPS;
+  static constexpr double x0 = BOYS_SCR_X0;
+  static constexpr double x1 = BOYS_SCR_X1;
+  static constexpr int rb_n = BOYS_SCR_RB_N, rb_m = BOYS_SCR_RB_M;
+  static constexpr int ra_n[kF64Kmax + 1] = BOYS_SCR_RA_DEG_N_INIT;
+  static constexpr int ra_m[kF64Kmax + 1] = BOYS_SCR_RA_DEG_M_INIT;
+  static constexpr double ra_p[kF64Kmax + 1][BOYS_SCR_RA_NMAX + 1] = BOYS_SCR_RA_P_INIT;
+  static constexpr double ra_q[kF64Kmax + 1][BOYS_SCR_RA_MMAX + 1] = BOYS_SCR_RA_Q_INIT;
+  static constexpr double rb_p[BOYS_SCR_RB_N + 1] = BOYS_SCR_RB_P_INIT;
+  static constexpr double rb_q[BOYS_SCR_RB_M + 1] = BOYS_SCR_RB_Q_INIT;
+};
+
+// The table set for a caller's error tolerance: the fastest set whose
+// guarantee is at most tol (1 = screening, 0 = the paper's), or -1 if none
+// is (tol below 5e-14, or NaN).
+__host__ __device__ constexpr int table_set_for(double tol) {
+  return tol >= ScreenTables::eps ? 1 : (tol >= PaperTables::eps ? 0 : -1);
+}
+
+// The paper's set under its short names (the batched consumer uses these).
+constexpr double kX0 = PaperTables::x0;
+constexpr double kX1 = PaperTables::x1;
+static constexpr auto &kRaN = PaperTables::ra_n;
+static constexpr auto &kRaM = PaperTables::ra_m;
+static constexpr auto &kRaP = PaperTables::ra_p;
+static constexpr auto &kRaQ = PaperTables::ra_q;
+static constexpr auto &kRbP = PaperTables::rb_p;
+static constexpr auto &kRbQ = PaperTables::rb_q;
 
 // Region C is open at x1.  The printed x1 is the double nearest the root of
 // the equation that defines it (asymptote error = eps_tol for F_32) but lies
 // just below the root, where the asymptote misses eps_tol by 8e-30; r_B was
-// fitted on the closed interval [x0, x1], so x = x1 is evaluated in B.
-__device__ __forceinline__ bool region_c(double x) { return x > kX1; }
+// fitted on the closed interval [x0, x1], so x = x1 is evaluated in B.  (The
+// screening x1 is the root rounded up.)
+template <class T = PaperTables>
+__device__ __forceinline__ bool region_c(double x) { return x > T::x1; }
 
 // r_{A,K}(x): Horner on numerator and (monic) denominator, one IEEE division.
-template <int K>
+template <int K, class T = PaperTables>
 __device__ __forceinline__ double rational_a(double x) {
-  constexpr int n = kRaN[K], m = kRaM[K];
-  double p = kRaP[K][n];
+  constexpr int n = T::ra_n[K], m = T::ra_m[K];
+  double p = T::ra_p[K][n];
 #pragma unroll
-  for (int i = n - 1; i >= 0; --i) p = __builtin_fma(p, x, kRaP[K][i]);
-  double q = x + kRaQ[K][m - 1];
+  for (int i = n - 1; i >= 0; --i) p = __builtin_fma(p, x, T::ra_p[K][i]);
+  double q = x + T::ra_q[K][m - 1];
 #pragma unroll
-  for (int i = m - 2; i >= 0; --i) q = __builtin_fma(q, x, kRaQ[K][i]);
+  for (int i = m - 2; i >= 0; --i) q = __builtin_fma(q, x, T::ra_q[K][i]);
   return p / q;
 }
 
 // r_B(x): F_0 on [x0, x1].
+template <class T = PaperTables>
 __device__ __forceinline__ double rational_b(double x) {
-  double p = kRbP[BOYS_RB_N];
+  double p = T::rb_p[T::rb_n];
 #pragma unroll
-  for (int i = BOYS_RB_N - 1; i >= 0; --i) p = __builtin_fma(p, x, kRbP[i]);
-  double q = x + kRbQ[BOYS_RB_M - 1];
+  for (int i = T::rb_n - 1; i >= 0; --i) p = __builtin_fma(p, x, T::rb_p[i]);
+  double q = x + T::rb_q[T::rb_m - 1];
 #pragma unroll
-  for (int i = BOYS_RB_M - 2; i >= 0; --i) q = __builtin_fma(q, x, kRbQ[i]);
+  for (int i = T::rb_m - 2; i >= 0; --i) q = __builtin_fma(q, x, T::rb_q[i]);
   return p / q;
 }
 
@@ -67,19 +111,19 @@ __device__ __forceinline__ double domain(double x) {
 // Divisions by the constants 2l+1 are multiplications by their rounded
 // reciprocals and 1/(2x) is formed once; each adds at most one rounding per
 // step to the error model of Appendix B.
-template <int K>
+template <int K, class T = PaperTables>
 __device__ __forceinline__ void boys_f64(double x, double (&F)[K + 1]) {
   x = domain(x);
   const double e = ::exp(-x);
-  if (x < kX0) {
-    F[K] = rational_a<K>(x);
+  if (x < T::x0) {
+    F[K] = rational_a<K, T>(x);
     const double two_x = x + x;
 #pragma unroll
     for (int l = K - 1; l >= 0; --l)
       F[l] = __builtin_fma(two_x, F[l + 1], e) * (1.0 / (2 * l + 1));
   } else {
-    const bool c = region_c(x);
-    const double f0b = rational_b(x);
+    const bool c = region_c<T>(x);
+    const double f0b = rational_b<T>(x);
     const double f0c = kHalfSqrtPi / ::sqrt(x);
     F[0] = c ? f0c : f0b;
     const double eb = c ? 0.0 : e;

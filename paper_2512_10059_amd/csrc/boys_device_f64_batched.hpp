@@ -132,6 +132,43 @@ __device__ __forceinline__ double rational_a_sc(double x) {
   return rational_loaded<kRaN[K], kRaM[K]>(x, kCoef.ra_p[K], kCoef.ra_q[K]);
 }
 
+// r_{A,K} and r_B of a table set T with compile-time order (the pair
+// kernel), straight from its monic rows.
+template <class T>
+constexpr bool monic_rows() {
+  for (int k = 0; k <= kF64Kmax; ++k)
+    if (T::ra_q[k][T::ra_m[k]] != 1.0) return false;
+  return T::rb_q[T::rb_m] == 1.0;
+}
+static_assert(monic_rows<PaperTables>() && monic_rows<ScreenTables>(), "denominators are monic");
+
+// The coefficients are indexed as compile-time constants (not through a
+// pointer), so they stay literals materialised where they are used; read
+// through a pointer they become scalar loads hoisted out of the pair loop,
+// which with the weights' 52 SGPRs spilled scalar registers.
+template <int K, class T>
+__device__ __forceinline__ double rational_a_t(double x) {
+  constexpr int n = T::ra_n[K], m = T::ra_m[K];
+  double p = T::ra_p[K][n];
+#pragma unroll
+  for (int i = n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::ra_p[K][i]);
+  double q = x + T::ra_q[K][m - 1];
+#pragma unroll
+  for (int i = m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::ra_q[K][i]);
+  return p / q;
+}
+
+template <class T>
+__device__ __forceinline__ double rational_b_t(double x) {
+  double p = T::rb_p[T::rb_n];
+#pragma unroll
+  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::rb_p[i]);
+  double q = x + T::rb_q[T::rb_m - 1];
+#pragma unroll
+  for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::rb_q[i]);
+  return p / q;
+}
+
 // r_B(x).
 __device__ __forceinline__ double rational_b_sc(double x) {
   return rational_loaded<BOYS_RB_N, BOYS_RB_M>(x, kCoef.rb_p, kCoef.rb_q);

@@ -30,7 +30,7 @@ __device__ __forceinline__ void store_nt(T *p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
-template <int K>
+template <int K, class T>
 __global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restrict__ x, int64_t n,
                                                           double *__restrict__ out, int64_t ld,
                                                           int contiguous) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restri
     const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     double F[C];
-    boys_f64<K>(i < n ? x[i] : 0.0, F);
+    boys_f64<K, T>(i < n ? x[i] : 0.0, F);
 #pragma unroll
     for (int l = 0; l < C; ++l) slice[lane * CP + l] = F[l];
     __syncthreads();
@@ -80,18 +80,27 @@ __global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restri
 
 using EvalKernel = void (*)(const double *, int64_t, double *, int64_t, int);
 
-template <std::size_t... K>
+template <class T, std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
-  return std::array<EvalKernel, sizeof...(K)>{{&eval_f64_kernel<int(K)>...}};
+  return std::array<EvalKernel, sizeof...(K)>{{&eval_f64_kernel<int(K), T>...}};
 }
-constexpr auto kEvalTable = make_table(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kEvalTable = make_table<PaperTables>(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kEvalTableScreen =
+    make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
 
 }  // namespace
 }  // namespace boys
 
 extern "C" int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, int64_t ld_out,
                              hipStream_t stream) {
+  return boys_eval_f64_tol(x, n, kmax, boys::PaperTables::eps, out, ld_out, stream);
+}
+
+extern "C" int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double tol, double *out,
+                                 int64_t ld_out, hipStream_t stream) {
   using namespace boys;
+  const int set = table_set_for(tol);
+  if (set < 0) return BOYS_EINVAL;
   if (n < 0 || kmax < 0 || kmax > kF64Kmax || ld_out < kmax + 1) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !out) return BOYS_EINVAL;
@@ -103,7 +112,7 @@ extern "C" int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, 
   const int contiguous = ld_out == kmax + 1 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
-  hipLaunchKernelGGL(kEvalTable[kmax], dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x, n, out,
-                     ld_out, contiguous);
+  hipLaunchKernelGGL(set == 1 ? kEvalTableScreen[kmax] : kEvalTable[kmax], dim3(unsigned(blocks)),
+                     dim3(kBlock), 0, stream, x, n, out, ld_out, contiguous);
   return hip_status(hipGetLastError());
 }

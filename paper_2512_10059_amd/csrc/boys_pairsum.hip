@@ -37,22 +37,23 @@ struct PairWeights {
   double c[kF64Kmax + 1];
 };
 
-// sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region.
-template <int K>
+// sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region,
+// with the table set T.
+template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
                                                 const PairWeights &dw, const double *s_exp) {
   double acc;
-  if (x < kX0) {
+  if (x < T::x0) {
     const double e = exp_neg(x, s_exp);
     const double two_x = x + x;
-    double F = rational_a_sc<K>(x);
+    double F = rational_a_t<K, T>(x);
     acc = cw.c[K] * F;
 #pragma unroll
     for (int l = K - 1; l >= 0; --l) {
       F = __builtin_fma(two_x, F, e) * (1.0 / (2 * l + 1));
       acc = __builtin_fma(cw.c[l], F, acc);
     }
-  } else if (region_c(x)) {
+  } else if (region_c<T>(x)) {
     // x^(-1/2) sum_l (c_l a_l) (1/x)^l by Horner in 1/x (F_l = a_l x^(-l-1/2)
     // beyond x1); x^(-1/2) and 1/x from one reciprocal square root r.
     const double r = ::rsqrt(x);
@@ -64,7 +65,7 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
   } else {  // region B (and NaN)
     const double e = exp_neg(x, s_exp);
     const double inv_2x = 0.5 / x;
-    double F = rational_b_sc(x);
+    double F = rational_b_t<T>(x);
     acc = cw.c[0] * F;
 #pragma unroll
     for (int l = 0; l < K; ++l) {
@@ -75,7 +76,7 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
   return acc;
 }
 
-template <int K>
+template <int K, class T>
 __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
                                                          const double *__restrict__ ys, int64_t n,
                                                          PairWeights cw, PairWeights dw,
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
     double part = 0.0;
     for (int t = 0; t < m; ++t)
-      part = __builtin_fma(s_y[t], pair_weighted<K>(domain(xi + s_x[t]), cw, dw, s_exp), part);
+      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + s_x[t]), cw, dw, s_exp), part);
     total += part;
     __syncthreads();
   }
@@ -123,11 +124,12 @@ __global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__r
 using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, PairWeights,
                             double *);
 
-template <std::size_t... K>
+template <class T, std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
-  return std::array<PairKernel, sizeof...(K)>{{&pairsum_kernel<int(K)>...}};
+  return std::array<PairKernel, sizeof...(K)>{{&pairsum_kernel<int(K), T>...}};
 }
-constexpr auto kPairTable = make_table(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kPairTable = make_table<PaperTables>(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kPairTableScreen = make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
 
 // Per-device workspace: sorted keys, indices, permuted y and z, sort scratch.
 struct PairState {
@@ -162,7 +164,14 @@ void pairsum_release_all() {
 
 extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const double *c, int kmax,
                             double *z, hipStream_t stream) {
+  return boys_pairsum_tol(x, y, n, c, kmax, boys::PaperTables::eps, z, stream);
+}
+
+extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, const double *c,
+                                int kmax, double tol, double *z, hipStream_t stream) {
   using namespace boys;
+  const int set = table_set_for(tol);
+  if (set < 0) return BOYS_EINVAL;
   if (n < 0 || n > (int64_t(1) << 31) - 1 || kmax < 0 || kmax > kF64Kmax) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !y || !c || !z) return BOYS_EINVAL;
@@ -223,7 +232,8 @@ extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const d
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(kPairTable[kmax], dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, dw, zs);
+  hipLaunchKernelGGL(set == 1 ? kPairTableScreen[kmax] : kPairTable[kmax], dim3(g), dim3(kBlock),
+                     0, stream, keys, ys, n, cw, dw, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
   return hip_status(hipGetLastError());

@@ -80,3 +80,23 @@ def test_argument_errors_without_gpu(lib):
     lib.boys_weighted_sum_set_config.argtypes = [I]
     assert lib.boys_weighted_sum_set_config(999) == EINVAL
     assert lib.boys_weighted_sum_num_configs() > 1
+
+
+def test_tolerance_argument_errors_without_gpu(lib):
+    """The accuracy-selecting entry points reject tolerances no table set
+    meets (below 5e-14, or NaN) before touching the GPU; an empty call with
+    a valid tolerance succeeds without a device."""
+    P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    f = lib.boys_eval_f64_tol
+    f.argtypes = [P, I64, I, D, P, I64, P]
+    dummy = P(4096)
+    for tol in (4.9e-14, 0.0, -1.0, float("nan")):
+        assert f(dummy, 10, 8, tol, dummy, 9, None) == EINVAL
+    assert f(dummy, 10, 33, 1e-10, dummy, 34, None) == EINVAL   # kmax > 32
+    for tol in (5e-14, 1e-12, 1e-10, 1.0, float("inf")):
+        assert f(dummy, 0, 8, tol, None, 9, None) == 0           # empty: nothing to do
+    p = lib.boys_pairsum_tol
+    p.argtypes = [P, P, I64, P, I, D, P, P]
+    assert p(dummy, dummy, 10, dummy, 4, 1e-15, dummy, None) == EINVAL
+    assert p(dummy, dummy, 10, dummy, 4, float("nan"), dummy, None) == EINVAL
+    assert p(dummy, dummy, 0, dummy, 4, 1e-10, dummy, None) == 0
