@@ -99,11 +99,15 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
     int64_t ct[kScanPer], cc[kScanPer];
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
+      // Unconditional loads from an index clamped into the table, so all of
+      // them are in flight together; batches past the end count as empty.
       const int32_t b = first + i;
-      const int64_t n = b < nbatch && bn[b] > 0 ? bn[b] : 0;
-      const int k = b < nbatch ? bk[b] : 0;
+      const int32_t bc = b < nbatch ? b : nbatch - 1;
+      const int32_t nr = bn[bc];
+      const int kr = bk[bc];
+      const int64_t n = b < nbatch && nr > 0 ? nr : 0;
       ct[i] = (n + round_up) >> tile_shift;
-      cc[i] = ((n + 63) >> 6) * pass_cost(clamp_order(k));
+      cc[i] = ((n + 63) >> 6) * pass_cost(clamp_order(kr));
     }
     int64_t st = 0, sc = 0;
 #pragma unroll
