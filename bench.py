@@ -400,7 +400,7 @@ def main():
                    "n": wo["n"], "kmax": wo["kmax"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "eval_f64_kernel<32>",
+                     "kernel": "eval_f64_kernel<32, boys::PaperTables>",
                      "algorithmic_bytes_per_launch": wo["alg_bytes"]},
         "cpu_baseline": cpu,
         "legs": extra,

@@ -47,93 +47,33 @@ __device__ __forceinline__ void load_exp_table(double *s_tab) {
   for (int t = threadIdx.x; t < kExpTableLen; t += blockDim.x) s_tab[t] = kExp2Table[t];
 }
 
-// ---------------------------------------------------------------------------
-// Constants read with scalar loads.  A 64-bit constant written as a literal
-// costs two scalar moves at every use, and on a SIMD the scalar and vector
-// instructions of a wave share its issue slots; these tables are not const,
-// so the compiler fetches them with wide scalar loads (one per eight
-// doubles) instead.
-//
-// r_{A,k} is stored for fixed-length Horner passes: P with zeros above n_k,
-// Q monic with its leading 1 at m_k and zeros above.  The extra leading steps
-// compute 0*x + 0 = 0, then 0*x + 1 = 1, then 1*x + q_{m-1}, which is the
-// x + q_{m-1} of the exact-length pass rounded once, so the result is the
-// same to the last bit.  Orders k >= kSplitK all have (n, m) <= (8, 9);
-// lower orders take (8, 13).
-constexpr int kPadN = BOYS_RA_NMAX;
-constexpr int kPadM = BOYS_RA_MMAX;
-constexpr int kSplitK = 8;
-constexpr int kHiM = 9;
+// e^{-x} (see above).  The constants are literals; the Horner steps take
+// theirs as SGPR addends.
+constexpr double kExpInvL = BOYS_EXP_INV_L;
+constexpr double kExpLHi = BOYS_EXP_L_HI;
+constexpr double kExpLLo = BOYS_EXP_L_LO;
 
-struct CoefTables {
-  double ra_p[kF64Kmax + 1][kPadN + 1];
-  double ra_q[kF64Kmax + 1][kPadM + 1];
-  double rb_p[BOYS_RB_N + 1];
-  double rb_q[BOYS_RB_M + 1];  // monic: rb_q[m] = 1
-  double exp_c[8];             // 128/ln2, -L_hi, -L_lo, -5, 20, -60, 120, -1/120
-};
-
-constexpr CoefTables make_coef_tables() {
-  CoefTables t{};
-  for (int k = 0; k <= kF64Kmax; ++k) {
-    for (int i = 0; i <= kRaN[k]; ++i) t.ra_p[k][i] = kRaP[k][i];
-    for (int i = 0; i < kRaM[k]; ++i) t.ra_q[k][i] = kRaQ[k][i];
-    t.ra_q[k][kRaM[k]] = 1.0;
-  }
-  for (int i = 0; i <= BOYS_RB_N; ++i) t.rb_p[i] = kRbP[i];
-  for (int i = 0; i < BOYS_RB_M; ++i) t.rb_q[i] = kRbQ[i];
-  t.rb_q[BOYS_RB_M] = 1.0;
-  const double c[8] = {BOYS_EXP_INV_L, -BOYS_EXP_L_HI, -BOYS_EXP_L_LO, -5.0, 20.0, -60.0, 120.0,
-                       -1.0 / 120.0};
-  for (int i = 0; i < 8; ++i) t.exp_c[i] = c[i];
-  return t;
-}
-
-constexpr bool split_holds() {
-  for (int k = kSplitK; k <= kF64Kmax; ++k)
-    if (kRaN[k] > kPadN || kRaM[k] > kHiM) return false;
-  return true;
-}
-static_assert(split_holds(), "orders >= kSplitK must fit the (8, 9) pass");
-
-static __constant__ CoefTables kCoef = make_coef_tables();
-
-// e^{-x} (see above).
 __device__ __forceinline__ double exp_neg(double x, const double *s_tab) {
-  const double *c = kCoef.exp_c;
-  const double nd = __builtin_rint(x * c[0]);
-  double r = __builtin_fma(nd, c[1], x);
-  r = __builtin_fma(nd, c[2], r);
+  const double nd = __builtin_rint(x * kExpInvL);
+  double r = __builtin_fma(-nd, kExpLHi, x);
+  r = __builtin_fma(-nd, kExpLLo, r);
   const int N = -int(nd);
   const double T = s_tab[N & (kExpTableLen - 1)];
-  double v = r + c[3];
-  v = fma_uniform_addend(v, r, c[4]);
-  v = fma_uniform_addend(v, r, c[5]);
-  v = fma_uniform_addend(v, r, c[6]);
-  const double q = (r * c[7]) * v;  // e^{-r} - 1
+  double v = r - 5.0;
+  v = fma_uniform_addend(v, r, 20.0);
+  v = fma_uniform_addend(v, r, -60.0);
+  v = fma_uniform_addend(v, r, 120.0);
+  const double q = (r * (-1.0 / 120.0)) * v;  // e^{-r} - 1
   return __builtin_amdgcn_ldexp(__builtin_fma(T, q, T), N >> BOYS_EXP_TABLE_BITS);
 }
 
-// p(x)/q(x) by Horner passes of NP and NQ steps over P[0..NP], Q[0..NQ].
-template <int NP, int NQ>
-__device__ __forceinline__ double rational_loaded(double x, const double *P, const double *Q) {
-  double p = P[NP];
-#pragma unroll
-  for (int i = NP - 1; i >= 0; --i) p = fma_uniform_addend(p, x, P[i]);
-  double q = Q[NQ];
-#pragma unroll
-  for (int i = NQ - 1; i >= 0; --i) q = fma_uniform_addend(q, x, Q[i]);
-  return p / q;
-}
-
-// r_{A,K}(x) for a compile-time order (exact degrees).
-template <int K>
-__device__ __forceinline__ double rational_a_sc(double x) {
-  return rational_loaded<kRaN[K], kRaM[K]>(x, kCoef.ra_p[K], kCoef.ra_q[K]);
-}
-
-// r_{A,K} and r_B of a table set T with compile-time order (the pair
-// kernel), straight from its monic rows.
+// ---------------------------------------------------------------------------
+// r_{A,K} and r_B of a table set T at a compile-time order (the pair kernel
+// and region B).  The coefficients are indexed as compile-time constants, so
+// they are literals materialised where they are used (two scalar moves per
+// coefficient, SGPR addends of the Horner steps); read through a pointer they
+// became scalar loads hoisted out of the pair loop, which together with the
+// weights' 52 SGPRs spilled scalar registers.
 template <class T>
 constexpr bool monic_rows() {
   for (int k = 0; k <= kF64Kmax; ++k)
@@ -142,10 +82,6 @@ constexpr bool monic_rows() {
 }
 static_assert(monic_rows<PaperTables>() && monic_rows<ScreenTables>(), "denominators are monic");
 
-// The coefficients are indexed as compile-time constants (not through a
-// pointer), so they stay literals materialised where they are used; read
-// through a pointer they become scalar loads hoisted out of the pair loop,
-// which with the weights' 52 SGPRs spilled scalar registers.
 template <int K, class T>
 __device__ __forceinline__ double rational_a_t(double x) {
   constexpr int n = T::ra_n[K], m = T::ra_m[K];
@@ -169,16 +105,59 @@ __device__ __forceinline__ double rational_b_t(double x) {
   return p / q;
 }
 
-// r_B(x).
-__device__ __forceinline__ double rational_b_sc(double x) {
-  return rational_loaded<BOYS_RB_N, BOYS_RB_M>(x, kCoef.rb_p, kCoef.rb_q);
+// ---------------------------------------------------------------------------
+// r_{A,k} for a runtime, wave-uniform k (the batched consumer).  The rows
+// live in a constant-memory table read with wide scalar loads at the
+// address of row k, instead of a 33-way branch to literal-coded passes.  Rows
+// are stored for fixed-length Horner passes: P with zeros above n_k, Q monic
+// with its leading 1 at m_k and zeros above.  The extra leading steps compute
+// 0*x + 0 = 0, then 0*x + 1 = 1, then 1*x + q_{m-1}, which is the
+// x + q_{m-1} of the exact-length pass rounded once, so the result is the
+// same to the last bit.  Orders k >= kSplitK all have (n, m) <= (8, 9); lower
+// orders take (8, 13).
+constexpr int kPadN = BOYS_RA_NMAX;
+constexpr int kPadM = BOYS_RA_MMAX;
+constexpr int kSplitK = 8;
+constexpr int kHiM = 9;
+
+struct RaRows {
+  double p[kF64Kmax + 1][kPadN + 1];
+  double q[kF64Kmax + 1][kPadM + 1];
+};
+
+constexpr RaRows make_ra_rows() {
+  RaRows t{};
+  for (int k = 0; k <= kF64Kmax; ++k) {
+    for (int i = 0; i <= kRaN[k]; ++i) t.p[k][i] = kRaP[k][i];
+    for (int i = 0; i <= kRaM[k]; ++i) t.q[k][i] = kRaQ[k][i];
+  }
+  return t;
 }
 
-// r_{A,k}(x) for a wave-uniform k in [0, 32]: one of two fixed-length passes
-// over the padded row of k.
+constexpr bool split_holds() {
+  for (int k = kSplitK; k <= kF64Kmax; ++k)
+    if (kRaN[k] > kPadN || kRaM[k] > kHiM) return false;
+  return true;
+}
+static_assert(split_holds(), "orders >= kSplitK must fit the (8, 9) pass");
+
+static __constant__ const RaRows kRaRows = make_ra_rows();
+
+// p(x)/q(x) by Horner passes of NP and NQ steps over P[0..NP], Q[0..NQ].
+template <int NP, int NQ>
+__device__ __forceinline__ double rational_loaded(double x, const double *P, const double *Q) {
+  double p = P[NP];
+#pragma unroll
+  for (int i = NP - 1; i >= 0; --i) p = fma_uniform_addend(p, x, P[i]);
+  double q = Q[NQ];
+#pragma unroll
+  for (int i = NQ - 1; i >= 0; --i) q = fma_uniform_addend(q, x, Q[i]);
+  return p / q;
+}
+
 __device__ __forceinline__ double rational_a_rt(double x, int k) {
-  const double *P = kCoef.ra_p[k];
-  const double *Q = kCoef.ra_q[k];
+  const double *P = kRaRows.p[k];
+  const double *Q = kRaRows.q[k];
   if (k < kSplitK) return rational_loaded<kPadN, kPadM>(x, P, Q);
   return rational_loaded<kPadN, kHiM>(x, P, Q);
 }
@@ -240,7 +219,7 @@ __device__ __forceinline__ double wsum_region_b(double x, int k, double w0, cons
                                                 const double *s_exp) {
   const double e = exp_neg(x, s_exp);
   const double inv_2x = 0.5 / x;
-  double F = rational_b_sc(x);
+  double F = rational_b_t<PaperTables>(x);
   double acc = w0 * F;
   for (int l0 = 0; l0 < k; l0 += kChunk) {
     wpair t[kChunk];
