@@ -37,11 +37,38 @@ struct PairWeights {
   double c[kF64Kmax + 1];
 };
 
+// Region B in closed form.  With g = 1/(2x) the upward recurrence
+// F_{l+1} = g ((2l+1) F_l - e^-x) unrolls to F_l = A_l(g) F_0 - e^-x B_l(g),
+//     A_l = (2l-1)!! g^l,   B_0 = 0,   B_{l+1} = g ((2l+1) B_l + 1),
+// so sum_l c_l F_l = F_0 P(g) - e^-x Q(g) with P(g) = sum_l c_l A_l(g) and
+// Q(g) = sum_l c_l B_l(g), polynomials in g whose coefficients depend only on
+// the weights (formed once per call on the host).  Two Horner passes take two
+// fused multiply-adds per order instead of a multiply and two fused
+// multiply-adds.  From x0 on the recurrence does not amplify errors
+// (prod (n+1/2)/x <= 1), so |c_l A_l F_0| and |c_l e B_l| stay below
+// |c_l| F_0: the absolute rounding stays on the scale of the recurrence's,
+// and an error in F_0 propagates as A_l, exactly as through the recurrence.
+struct PairBPoly {
+  double p[kF64Kmax + 1];  // coefficients of P, degree 0 upwards
+  double q[kF64Kmax + 1];  // coefficients of Q (q[0] = 0)
+};
+
+// 1/x for finite x in the normal range: the hardware reciprocal refined by
+// two Newton steps (within about one ulp).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region,
 // with the table set T.
 template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
-                                                const PairWeights &dw, const double *s_exp) {
+                                                const PairWeights &dw, const wpair *pq,
+                                                const double *s_exp) {
   double acc;
   if (x < T::x0) {
     const double e = exp_neg(x, s_exp);
@@ -62,16 +89,31 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
 #pragma unroll
     for (int l = K - 1; l >= 0; --l) P = fma_uniform_addend(P, g, dw.c[l]);
     acc = P * r;
-  } else {  // region B (and NaN)
+  } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l)
     const double e = exp_neg(x, s_exp);
-    const double inv_2x = 0.5 / x;
-    double F = rational_b_t<T>(x);
-    acc = cw.c[0] * F;
+    const double g = 0.5 * recip(x);
+    const double F0 = rational_b_t<T>(x);
+    // Chunks of four steps (one chunk rolled), so at most four coefficient
+    // pairs are in registers; K % 4 leading steps first.
+    double P = pq[K].x, Q = pq[K].y;
+    int l = K - 1;
 #pragma unroll
-    for (int l = 0; l < K; ++l) {
-      F = __builtin_fma(double(2 * l + 1), F, -e) * inv_2x;
-      acc = __builtin_fma(cw.c[l + 1], F, acc);
+    for (int s = 0; s < K % 4; ++s, --l) {
+      P = __builtin_fma(P, g, pq[l].x);
+      Q = __builtin_fma(Q, g, pq[l].y);
     }
+#pragma unroll 1
+    for (; l >= 0; l -= 4) {
+      wpair t[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) t[s] = pq[l - s];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        P = __builtin_fma(P, g, t[s].x);
+        Q = __builtin_fma(Q, g, t[s].y);
+      }
+    }
+    acc = __builtin_fma(F0, P, -(e * Q));
   }
   return acc;
 }
@@ -79,11 +121,13 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
 template <int K, class T>
 __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
                                                          const double *__restrict__ ys, int64_t n,
-                                                         PairWeights cw, PairWeights dw,
+                                                         PairWeights cw, PairWeights dw, PairBPoly bp,
                                                          double *__restrict__ zs) {
   __shared__ double s_x[kPairChunk], s_y[kPairChunk];
   __shared__ double s_exp[kExpTableLen];
+  __shared__ wpair s_pq[K + 1];
   load_exp_table(s_exp);  // made visible by the first barrier below
+  if (threadIdx.x <= K) s_pq[threadIdx.x] = wpair{bp.p[threadIdx.x], bp.q[threadIdx.x]};
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   double total = 0.0;
@@ -97,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
     double part = 0.0;
     for (int t = 0; t < m; ++t)
-      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + s_x[t]), cw, dw, s_exp), part);
+      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + s_x[t]), cw, dw, s_pq, s_exp), part);
     total += part;
     __syncthreads();
   }
@@ -122,7 +166,7 @@ __global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__r
 }
 
 using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, PairWeights,
-                            double *);
+                            PairBPoly, double *);
 
 template <class T, std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
@@ -186,6 +230,24 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
     cw.c[l] = c[l];
     dw.c[l] = c[l] * kAsymCoefHost[l];
   }
+  // Region B's polynomials P and Q (see PairBPoly), in long double:
+  // A_l = a_l g^l with a_l = (2l-1)!!, B_l = sum_j b_j g^j.
+  PairBPoly bp{};
+  {
+    long double a = 1.0L, b[kF64Kmax + 2] = {}, pq_p[kF64Kmax + 1] = {}, pq_q[kF64Kmax + 1] = {};
+    for (int l = 0; l <= kmax; ++l) {
+      pq_p[l] = (long double)c[l] * a;
+      for (int j = 1; j <= l; ++j) pq_q[j] += (long double)c[l] * b[j];
+      // B_{l+1} = g ((2l+1) B_l + 1): shift up by one power of g.
+      for (int j = l + 1; j >= 2; --j) b[j] = (2 * l + 1) * b[j - 1];
+      b[1] = 1.0L;
+      a *= 2 * l + 1;
+    }
+    for (int l = 0; l <= kmax; ++l) {
+      bp.p[l] = double(pq_p[l]);
+      bp.q[l] = double(pq_q[l]);
+    }
+  }
 
   size_t sort_bytes = 0;
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, static_cast<const double *>(nullptr),
@@ -233,7 +295,7 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(set == 1 ? kPairTableScreen[kmax] : kPairTable[kmax], dim3(g), dim3(kBlock),
-                     0, stream, keys, ys, n, cw, dw, zs);
+                     0, stream, keys, ys, n, cw, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
   return hip_status(hipGetLastError());

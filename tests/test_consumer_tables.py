@@ -143,3 +143,59 @@ def test_asymptote_coefficients_reproduce_the_recurrence():
         for l, a in enumerate(C["asym"]):
             assert abs(mp.mpf(a) * mp.mpf(x) ** (-l - mp.mpf(1) / 2) / F - 1) < mp.mpf(2.0 ** -52)
             F = F * (l + mp.mpf(1) / 2) / x
+
+
+def region_b_polys(c):
+    """P and Q of the pair kernel's region-B closed form, built by the same
+    rules as the library's host code: A_l = (2l-1)!! g^l, B_0 = 0,
+    B_{l+1} = g ((2l+1) B_l + 1); P = sum c_l A_l, Q = sum c_l B_l."""
+    K = len(c) - 1
+    a, b = mp.mpf(1), [mp.mpf(0)] * (K + 2)
+    p, q = [mp.mpf(0)] * (K + 1), [mp.mpf(0)] * (K + 1)
+    for l in range(K + 1):
+        p[l] = c[l] * a
+        for j in range(1, l + 1):
+            q[j] += c[l] * b[j]
+        for j in range(l + 1, 1, -1):
+            b[j] = (2 * l + 1) * b[j - 1]
+        b[1] = mp.mpf(1)
+        a *= 2 * l + 1
+    return p, q
+
+
+@pytest.mark.parametrize("K", [0, 1, 5, 12, 32])
+def test_region_b_closed_form_equals_the_upward_recurrence(K):
+    """sum_l c_l F_l with F_{l+1} = ((2l+1) F_l - e^-x)/(2x) from any F_0 equals
+    F_0 P(g) - e^-x Q(g), g = 1/(2x) (identity of the recurrence, checked in
+    50-digit arithmetic for arbitrary F_0 and weights)."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(K)
+    c = [mp.mpf(float(v)) for v in rng.standard_normal(K + 1)]
+    p, q = region_b_polys(c)
+    for x in (11.9, 15.0, 23.0, 28.98):
+        x = mp.mpf(x)
+        e = mp.exp(-x)
+        F = mp.mpf(float(rng.uniform(0.1, 1.0)))  # any starting value
+        g = 1 / (2 * x)
+        closed = F * mp.polyval(p[::-1], g) - e * mp.polyval(q[::-1], g)
+        s = c[0] * F
+        for l in range(K):
+            F = ((2 * l + 1) * F - e) / (2 * x)
+            s += c[l + 1] * F
+        assert abs(closed - s) <= mp.mpf(10) ** -40 * (1 + abs(s))
+
+
+def test_region_b_closed_form_check_detects_a_wrong_shift():
+    """A mutant of the construction (B_{l+1} without the shift by g) fails."""
+    mp.mp.dps = 50
+    c = [mp.mpf(v) for v in (0.3, -1.2, 0.7, 2.0)]
+    p, q = region_b_polys(c)
+    q_bad = q[1:] + [mp.mpf(0)]
+    x = mp.mpf(13.0)
+    e, g, F = mp.exp(-x), 1 / (2 * mp.mpf(13.0)), mp.mpf(0.5)
+    s = c[0] * F
+    for l in range(3):
+        F = ((2 * l + 1) * F - e) / (2 * x)
+        s += c[l + 1] * F
+    bad = mp.mpf(0.5) * mp.polyval(p[::-1], g) - e * mp.polyval(q_bad[::-1], g)
+    assert abs(bad - s) > mp.mpf(10) ** -10
