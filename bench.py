@@ -18,10 +18,11 @@ Beside the headline the same JSON line carries:
                 (2^24 arguments, kmax=16, forward + backward), the paper's
                 own N^2 benchmark (n = 2^19, k = 12) beside its A100 time, and
                 the screening table set (eps_tol = 1e-10) on the write-out
-                and pair-sum workloads.
+                and pair-sum workloads, and the write-out at kmax = 40 (the
+                high-order tables).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
-       [--only writeout,fp32,fused,backward,pairsum,screen]
+       [--only writeout,fp32,fused,backward,pairsum,screen,high]
        [--no-cpu-baseline] [--copy-probe]
 """
 from __future__ import annotations
@@ -265,6 +266,26 @@ def leg_screen(torch, boys, workloads, steps, warmup, dev, wo=None):
             "pairsum_pairs_per_s": float(pn) * pn / ps, "_out": out}
 
 
+def leg_high(torch, boys, workloads, steps, warmup, dev, wo=None):
+    """Orders up to 40 (the high-order tables, 5e-14): the headline write-out
+    workload at kmax = 40, a 2^26 x 41 FP64 output (22.5 GB per launch)."""
+    n, kmax = workloads.N_WRITEOUT, 40
+    x = wo["x"] if wo else torch.from_numpy(workloads.gaussian_pair_arguments(n)).to(dev)
+    out = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        boys.boys_eval_f64(x, kmax, out=out)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            boys.boys_eval_f64(x, kmax, out=out)
+    ms = t.ms / steps
+    log(f"high orders: write-out kmax=40 {ms:.3f} ms")
+    res = {"kmax": kmax, "writeout_ms": ms, "writeout_values_per_s": n * (kmax + 1) / (ms * 1e-3),
+           "writeout_gbs": n * 8 * (kmax + 2) / (ms * 1e6)}
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline_leg(torch, wo, fp32, screen=None):
     """The oracle on the first 2^24 write-out arguments, all host cores; the
     GPU rows of the same arguments are compared with it on the way."""
@@ -318,7 +339,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum,screen")
+    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum,screen,high")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -373,6 +394,11 @@ def main():
             extra["screen"] = {k: v for k, v in screen.items() if not k.startswith("_")}
         except Exception as e:
             extra["screen"] = {"error": str(e)}
+    if "high" in legs:
+        try:
+            extra["high"] = leg_high(torch, boys, workloads, args.steps, args.warmup, dev, wo)
+        except Exception as e:
+            extra["high"] = {"error": str(e)}
     if wo is None:  # profiling runs of single legs
         print(json.dumps({"legs": extra}))
         return

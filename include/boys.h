@@ -58,8 +58,11 @@ enum {
     BOYS_ENOMEM = -4    /* the workspace could not be allocated */
 };
 
-/* Highest order of the FP64 tables, and of the FP32 tables. */
+/* Highest order of the paper's FP64 tables (every FP64 entry point), of the
+ * high-order FP64 tables (boys_eval_f64 and boys_eval_f64_tol only), and of
+ * the FP32 tables. */
 #define BOYS_F64_KMAX_LIMIT 32
+#define BOYS_F64_EVAL_KMAX_LIMIT 40
 #define BOYS_F32_KMAX_LIMIT 16
 
 /* Text for a status code (static storage, never NULL). */
@@ -74,7 +77,11 @@ BOYS_API int boys_last_hip_error(void);
  *   x      [n] FP64 arguments.
  *   out    row-major n x ld_out FP64: out[i*ld_out + k] = F_k(x[i]) for
  *          k = 0..kmax; columns kmax+1..ld_out-1 are left untouched.
- *   kmax   0 <= kmax <= 32; r_{A,kmax} is the region-A approximant used.
+ *   kmax   0 <= kmax <= 40.  Up to 32 the paper's tables (r_{A,kmax} is the
+ *          region-A approximant used); 33..40 a table set built the same way
+ *          for kmax = 40 at the same 5e-14 (x0 = 14.842842360917231, x1 and
+ *          every rational from the library's Remez tool), whose guarantee
+ *          is the same |error| <= 5e-14.
  *   ld_out row stride in elements, ld_out >= kmax + 1.
  * Errors: BOYS_EINVAL for n < 0, kmax out of range, ld_out too small, a null
  * pointer with n > 0, or x and out overlapping.
@@ -92,8 +99,9 @@ BOYS_API int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, in
  *                  library's Remez tool (Walsh-table degree choice, lower
  *                  degrees than the paper's); |error| <= 1e-10.
  *   tol >= 5e-14   the paper's tables (identical to boys_eval_f64).
- * Arguments and layout as boys_eval_f64.  Errors: as boys_eval_f64, and
- * BOYS_EINVAL for tol < 5e-14 or NaN.
+ * Orders 33..40 exist only at 5e-14 (the high-order tables) and take them
+ * for any tol >= 5e-14.  Arguments and layout as boys_eval_f64.  Errors: as
+ * boys_eval_f64, and BOYS_EINVAL for tol < 5e-14 or NaN.
  */
 BOYS_API int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double tol, double *out,
                                int64_t ld_out, hipStream_t stream);

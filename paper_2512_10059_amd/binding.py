@@ -16,7 +16,8 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libboys.so")
 _lib = None
 
-F64_KMAX = 32
+F64_KMAX = 32        # the paper's tables: every FP64 entry point
+F64_KMAX_EVAL = 40   # boys_eval_f64(_tol): orders 33..40 use the high-order tables
 F32_KMAX = 16
 
 _P = ctypes.c_void_p
@@ -118,7 +119,7 @@ def _eval(name: str, x: torch.Tensor, kmax: int, out, dtype, limit: int):
 
 def boys_eval_f64(x: torch.Tensor, kmax: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """F_0..F_kmax(x) in FP64 as an (n, kmax+1) tensor (or into ``out``)."""
-    return _eval("boys_eval_f64", x, kmax, out, torch.float64, F64_KMAX)
+    return _eval("boys_eval_f64", x, kmax, out, torch.float64, F64_KMAX_EVAL)
 
 
 def boys_eval_f64_tol(x: torch.Tensor, kmax: int, tol: float,
@@ -126,8 +127,8 @@ def boys_eval_f64_tol(x: torch.Tensor, kmax: int, tol: float,
     """boys_eval_f64 with the cheaper table set whose guarantee is at most tol
     (tol >= 1e-10: the screening set; tol >= 5e-14: the paper's)."""
     _vector(x, torch.float64, "x")
-    if not 0 <= kmax <= F64_KMAX:
-        raise BoysError(f"kmax must be in [0, {F64_KMAX}]")
+    if not 0 <= kmax <= F64_KMAX_EVAL:
+        raise BoysError(f"kmax must be in [0, {F64_KMAX_EVAL}]")
     n = x.numel()
     if out is None:
         out = torch.empty((n, kmax + 1), dtype=torch.float64, device=x.device)

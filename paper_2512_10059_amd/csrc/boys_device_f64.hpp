@@ -8,6 +8,7 @@
 
 #include "boys_coeffs_f64.h"
 #include "boys_coeffs_f64_screen.h"
+#include "boys_coeffs_f64_high.h"
 
 namespace boys {
 
@@ -15,12 +16,14 @@ constexpr int kF64Kmax = BOYS_F64_KMAX;
 constexpr double kHalfSqrtPi = 0.88622692545275801364908374167057259;
 
 // A table set of the method: region constants and the coefficients of r_B
-// and r_{A,k}, k = 0..32, from degree 0 upwards with monic denominators
-// (q[m] = 1).  PaperTables are the appendix's (eps_tol = 5e-14, Sec. II F);
-// ScreenTables are the same construction at eps_tol = 1e-10 (same x0, which
-// depends only on kmax; x1 from the asymptote-error equation at 1e-10; the
-// rationals from the Remez tool with the Walsh-table degree choice).
+// and r_{A,k}, k = 0..kmax, from degree 0 upwards with monic denominators
+// (q[m] = 1).  PaperTables are the appendix's (eps_tol = 5e-14, kmax = 32,
+// Sec. II F).  The others repeat the construction with the Remez tool and the
+// Walsh-table degree choice: ScreenTables at eps_tol = 1e-10 (same x0, which
+// depends only on kmax; x1 from the asymptote-error equation at 1e-10), and
+// HighTables at 5e-14 for orders up to 40 (x0 and x1 of kmax = 40).
 struct PaperTables {
+  static constexpr int kmax = kF64Kmax;
   static constexpr double eps = 5e-14;
   static constexpr double x0 = BOYS_F64_X0;  // A = [0, x0)
   static constexpr double x1 = BOYS_F64_X1;  // C = (x1, inf), see region_c()
@@ -34,6 +37,7 @@ struct PaperTables {
 };
 
 struct ScreenTables {
+  static constexpr int kmax = BOYS_SCR_KMAX;
   static constexpr double eps = BOYS_SCR_EPS;
   static constexpr double x0 = BOYS_SCR_X0;
   static constexpr double x1 = BOYS_SCR_X1;
@@ -46,11 +50,32 @@ struct ScreenTables {
   static constexpr double rb_q[BOYS_SCR_RB_M + 1] = BOYS_SCR_RB_Q_INIT;
 };
 
-// The table set for a caller's error tolerance: the fastest set whose
-// guarantee is at most tol (1 = screening, 0 = the paper's), or -1 if none
-// is (tol below 5e-14, or NaN).
-__host__ __device__ constexpr int table_set_for(double tol) {
-  return tol >= ScreenTables::eps ? 1 : (tol >= PaperTables::eps ? 0 : -1);
+constexpr int kHighKmax = BOYS_HIGH_KMAX;
+struct HighTables {
+  static constexpr int kmax = kHighKmax;
+  static constexpr double eps = BOYS_HIGH_EPS;
+  static constexpr double x0 = BOYS_HIGH_X0;
+  static constexpr double x1 = BOYS_HIGH_X1;
+  static constexpr int rb_n = BOYS_HIGH_RB_N, rb_m = BOYS_HIGH_RB_M;
+  static constexpr int ra_n[kHighKmax + 1] = BOYS_HIGH_RA_DEG_N_INIT;
+  static constexpr int ra_m[kHighKmax + 1] = BOYS_HIGH_RA_DEG_M_INIT;
+  static constexpr double ra_p[kHighKmax + 1][BOYS_HIGH_RA_NMAX + 1] = BOYS_HIGH_RA_P_INIT;
+  static constexpr double ra_q[kHighKmax + 1][BOYS_HIGH_RA_MMAX + 1] = BOYS_HIGH_RA_Q_INIT;
+  static constexpr double rb_p[BOYS_HIGH_RB_N + 1] = BOYS_HIGH_RB_P_INIT;
+  static constexpr double rb_q[BOYS_HIGH_RB_M + 1] = BOYS_HIGH_RB_Q_INIT;
+};
+static_assert(ScreenTables::kmax == kF64Kmax && HighTables::eps == PaperTables::eps,
+              "the screening set covers the paper's orders; the high-order set its accuracy");
+
+// The table set for a caller's order and error tolerance: the cheapest set
+// that covers kmax and whose guarantee is at most tol (1 = screening, 0 = the
+// paper's, 2 = high orders), or -1 if none does (tol below 5e-14 or NaN, or
+// kmax above 40).
+enum TableSet { kSetNone = -1, kSetPaper = 0, kSetScreen = 1, kSetHigh = 2 };
+__host__ __device__ constexpr int table_set_for(int kmax, double tol) {
+  if (!(tol >= PaperTables::eps) || kmax < 0 || kmax > HighTables::kmax) return kSetNone;
+  if (kmax > PaperTables::kmax) return kSetHigh;
+  return tol >= ScreenTables::eps ? kSetScreen : kSetPaper;
 }
 
 // The paper's set under its short names (the batched consumer uses these).

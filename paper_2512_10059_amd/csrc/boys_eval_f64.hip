@@ -88,6 +88,16 @@ constexpr auto kEvalTable = make_table<PaperTables>(std::make_index_sequence<kF6
 constexpr auto kEvalTableScreen =
     make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
 
+// Orders above 32: the high-order set (its orders up to 32 are not needed:
+// the paper's tables cover them at the same accuracy).
+template <std::size_t... I>
+constexpr auto make_high_table(std::index_sequence<I...>) {
+  return std::array<EvalKernel, sizeof...(I)>{
+      {&eval_f64_kernel<kF64Kmax + 1 + int(I), HighTables>...}};
+}
+constexpr auto kEvalTableHigh =
+    make_high_table(std::make_index_sequence<kHighKmax - kF64Kmax>{});
+
 }  // namespace
 }  // namespace boys
 
@@ -99,9 +109,9 @@ extern "C" int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, 
 extern "C" int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double tol, double *out,
                                  int64_t ld_out, hipStream_t stream) {
   using namespace boys;
-  const int set = table_set_for(tol);
+  const int set = table_set_for(kmax, tol);
   if (set < 0) return BOYS_EINVAL;
-  if (n < 0 || kmax < 0 || kmax > kF64Kmax || ld_out < kmax + 1) return BOYS_EINVAL;
+  if (n < 0 || ld_out < kmax + 1) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !out) return BOYS_EINVAL;
   if (n - 1 > (INT64_MAX / 8 - (kmax + 1)) / ld_out) return BOYS_EINVAL;
@@ -112,7 +122,10 @@ extern "C" int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double to
   const int contiguous = ld_out == kmax + 1 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
-  hipLaunchKernelGGL(set == 1 ? kEvalTableScreen[kmax] : kEvalTable[kmax], dim3(unsigned(blocks)),
-                     dim3(kBlock), 0, stream, x, n, out, ld_out, contiguous);
+  const EvalKernel kernel = set == kSetHigh     ? kEvalTableHigh[kmax - kF64Kmax - 1]
+                           : set == kSetScreen ? kEvalTableScreen[kmax]
+                                               : kEvalTable[kmax];
+  hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x, n, out, ld_out,
+                     contiguous);
   return hip_status(hipGetLastError());
 }

@@ -214,9 +214,9 @@ extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const d
 extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, const double *c,
                                 int kmax, double tol, double *z, hipStream_t stream) {
   using namespace boys;
-  const int set = table_set_for(tol);
-  if (set < 0) return BOYS_EINVAL;
   if (n < 0 || n > (int64_t(1) << 31) - 1 || kmax < 0 || kmax > kF64Kmax) return BOYS_EINVAL;
+  const int set = table_set_for(kmax, tol);
+  if (set < 0) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !y || !c || !z) return BOYS_EINVAL;
   if (overlaps(z, n * 8, x, n * 8) || overlaps(z, n * 8, y, n * 8)) return BOYS_EINVAL;
@@ -294,7 +294,7 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(set == 1 ? kPairTableScreen[kmax] : kPairTable[kmax], dim3(g), dim3(kBlock),
+  hipLaunchKernelGGL(set == kSetScreen ? kPairTableScreen[kmax] : kPairTable[kmax], dim3(g), dim3(kBlock),
                      0, stream, keys, ys, n, cw, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);

@@ -56,7 +56,7 @@ def test_argument_errors_without_gpu(lib):
     f.argtypes = [P, I64, I, P, I64, P]
     dummy = P(4096)
     assert f(dummy, -1, 8, dummy, 9, None) == EINVAL       # n < 0
-    assert f(dummy, 10, 33, dummy, 34, None) == EINVAL     # kmax > 32
+    assert f(dummy, 10, 41, dummy, 42, None) == EINVAL     # kmax > 40
     assert f(dummy, 10, -1, dummy, 9, None) == EINVAL      # kmax < 0
     assert f(dummy, 10, 8, dummy, 8, None) == EINVAL       # ld_out < kmax+1
     assert f(None, 10, 8, dummy, 9, None) == EINVAL        # null x
@@ -92,7 +92,7 @@ def test_tolerance_argument_errors_without_gpu(lib):
     dummy = P(4096)
     for tol in (4.9e-14, 0.0, -1.0, float("nan")):
         assert f(dummy, 10, 8, tol, dummy, 9, None) == EINVAL
-    assert f(dummy, 10, 33, 1e-10, dummy, 34, None) == EINVAL   # kmax > 32
+    assert f(dummy, 10, 41, 1e-10, dummy, 42, None) == EINVAL   # kmax > 40
     for tol in (5e-14, 1e-12, 1e-10, 1.0, float("inf")):
         assert f(dummy, 0, 8, tol, None, 9, None) == 0           # empty: nothing to do
     p = lib.boys_pairsum_tol

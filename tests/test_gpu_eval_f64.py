@@ -110,7 +110,7 @@ def test_deterministic():
 def test_invalid_arguments_raise():
     x = torch.ones(10, dtype=torch.float64, device=DEV)
     with pytest.raises(boys.BoysError):
-        boys.boys_eval_f64(x, 33)
+        boys.boys_eval_f64(x, 41)
     with pytest.raises(boys.BoysError):
         boys.boys_eval_f64(x.float(), 3)
     out = torch.empty((10, 5), dtype=torch.float64, device=DEV)
