@@ -30,19 +30,29 @@ __device__ __forceinline__ void store_nt(T *p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// Waves per workgroup of the write-out kernel for order K.  The LDS stage
+// takes 64*(K+1)*8 bytes per wave; four-wave groups at orders above 32
+// (84 KB per group at order 40) fit one group, four waves, per CU, too few
+// to keep the stores in flight.  Those orders run two-wave groups (three to
+// four groups per CU).  Measured at 2^26 arguments: order 40 in 4.19 ms with
+// two-wave groups against 4.79 ms with four and 4.24 ms with one; staging 32
+// rows at a time to raise occupancy further, or a persistent grid, was slower.
+constexpr int eval_waves(int K) { return K > kF64Kmax ? 2 : kWavesPerBlock; }
+
 template <int K, class T>
-__global__ __launch_bounds__(kBlock) void eval_f64_kernel(const double *__restrict__ x, int64_t n,
-                                                          double *__restrict__ out, int64_t ld,
-                                                          int contiguous) {
+__global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
+    const double *__restrict__ x, int64_t n, double *__restrict__ out, int64_t ld,
+    int contiguous) {
   constexpr int C = K + 1;                      // doubles per output row
   constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // LDS row stride (odd)
-  __shared__ __attribute__((aligned(16))) double stage[kWavesPerBlock * 64 * CP];
+  constexpr int WB = eval_waves(K);
+  __shared__ __attribute__((aligned(16))) double stage[WB * 64 * CP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double *slice = stage + wave * 64 * CP;
 
-  for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
-    const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
+  for (int64_t blk = blockIdx.x; blk * (64 * WB) < n; blk += gridDim.x) {
+    const int64_t row0 = blk * (64 * WB) + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     double F[C];
     boys_f64<K, T>(i < n ? x[i] : 0.0, F);
@@ -120,12 +130,13 @@ extern "C" int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double to
   if (int st = check_device()) return st;
 
   const int contiguous = ld_out == kmax + 1 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-  int64_t blocks = (n + kBlock - 1) / kBlock;
+  const int block = 64 * eval_waves(kmax);
+  int64_t blocks = (n + block - 1) / block;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
   const EvalKernel kernel = set == kSetHigh     ? kEvalTableHigh[kmax - kF64Kmax - 1]
                            : set == kSetScreen ? kEvalTableScreen[kmax]
                                                : kEvalTable[kmax];
-  hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x, n, out, ld_out,
+  hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(block), 0, stream, x, n, out, ld_out,
                      contiguous);
   return hip_status(hipGetLastError());
 }
