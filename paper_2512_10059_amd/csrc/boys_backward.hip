@@ -9,10 +9,10 @@
 // order kmax+1 instead of reading values saved by the forward pass: x is
 // 8 bytes per argument while the saved rows would be 8*(kmax+1).  G rows are
 // the dominant traffic (8*(kmax+1) bytes per argument); each wave reads its
-// 64 rows as one contiguous stream (all loads issued before the evaluation,
-// which hides their latency) into an LDS slice whose row stride is padded to
-// an odd number of doubles, so that the per-lane row reads that follow are
-// free of bank conflicts.
+// 64 rows as one contiguous stream (16-byte loads when the rows are packed;
+// all loads issued before the evaluation, which hides their latency) into an
+// LDS slice whose row stride is padded to an odd number of doubles, so that
+// the per-lane row reads that follow are free of bank conflicts.
 #include <hip/hip_runtime.h>
 
 #include <array>
@@ -26,10 +26,13 @@
 namespace boys {
 namespace {
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restrict__ x,
                                                           const double *__restrict__ g, int64_t n,
-                                                          int64_t ld, double *__restrict__ grad) {
+                                                          int64_t ld, double *__restrict__ grad,
+                                                          int packed) {
   constexpr int C = K + 1;                  // columns of G used
   constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // padded LDS row stride
   __shared__ double stage[kWavesPerBlock * 64 * CP];
@@ -42,7 +45,32 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
     const int64_t i = row0 + lane;
     const int rows = n - row0 < 64 ? int(n - row0 > 0 ? n - row0 : 0) : 64;
     double F[C + 1];
-    if (rows == 64) {
+    if (rows == 64 && packed) {
+      // Full wave, packed 16-byte-aligned rows: the wave's 64 rows are 32*C
+      // consecutive 16-byte units, read with 16-byte loads (1 KiB per
+      // instruction), all issued before the evaluation.  A unit may straddle
+      // two rows when C is odd; its halves go to their own LDS rows.
+      constexpr int U = 32 * C;
+      constexpr int J = (U + 63) / 64;
+      const d2 *src = reinterpret_cast<const d2 *>(g + row0 * C);
+      d2 gv[J];
+#pragma unroll
+      for (int jj = 0; jj < J; ++jj) {
+        const int u = lane + 64 * jj;
+        gv[jj] = __builtin_nontemporal_load(src + (u < U ? u : U - 1));
+      }
+      boys_f64<K + 1>(x[i], F);
+#pragma unroll
+      for (int jj = 0; jj < J; ++jj) {
+        const int u = lane + 64 * jj;
+        if (u < U) {
+          const int e = 2 * u, r = e / C, c = e - r * C;
+          slice[r * CP + c] = gv[jj].x;
+          const int r1 = (e + 1) / C, c1 = e + 1 - r1 * C;
+          slice[r1 * CP + c1] = gv[jj].y;
+        }
+      }
+    } else if (rows == 64) {
       // Full wave: issue all C loads of this wave's 64 rows of G (64
       // consecutive elements per instruction when the rows are packed)
       // before the evaluation, so their latency hides behind it.
@@ -76,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
   }
 }
 
-using BackwardKernel = void (*)(const double *, const double *, int64_t, int64_t, double *);
+using BackwardKernel = void (*)(const double *, const double *, int64_t, int64_t, double *, int);
 
 template <std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
@@ -101,7 +129,8 @@ extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, i
 
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
+  const int packed = ld_g == kmax + 1 && (reinterpret_cast<uintptr_t>(grad_f) & 15) == 0;
   hipLaunchKernelGGL(kBackwardTable[kmax], dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x,
-                     grad_f, n, ld_g, grad_x);
+                     grad_f, n, ld_g, grad_x, packed);
   return hip_status(hipGetLastError());
 }

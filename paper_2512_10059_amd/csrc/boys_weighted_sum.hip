@@ -18,8 +18,9 @@
 // Divergence.  Argument streams mix all three regions inside every wave, and
 // Algorithm 1 takes a different path in each.  With binning enabled the wave
 // first sorts its tile by region in LDS (ballot and bit-count ranks), so every
-// 64-lane pass except at most two runs a single path; results are scattered
-// back to their original positions inside the tile.
+// 64-lane pass except at most two runs a single path; results go back into
+// the sorted slots and leave the tile in the original order, each lane
+// reading its own items' slots, so the output stores stay coalesced.
 //
 // The scan and the persistent kernel are launched as one cached hipGraph per
 // device; the graph is rebuilt when any argument or the configuration
@@ -69,9 +70,6 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
   const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
   return int64_t((uint64_t(hi) << 32) | lo);
-}
-__device__ __forceinline__ double uniform(double v) {
-  return __builtin_bit_cast(double, uniform(__builtin_bit_cast(int64_t, v)));
 }
 
 // Exclusive prefix sums of tiles and cost over the batches (one workgroup).
@@ -246,8 +244,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   constexpr int T = 64 * ITEMS;
   __shared__ wpair s_down[kWavesPerBlock][kTableLen];  // (w_l, 1/(2l+1))
   __shared__ wpair s_up[kWavesPerBlock][kTableLen];    // (w_{l+1}, 2l+1)
-  __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];
-  __shared__ int s_idx[kWavesPerBlock][BIN ? T : 1];
+  __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];  // sorted arguments, then their results
   __shared__ double s_exp[kExpTableLen];
   __shared__ __attribute__((aligned(16))) double s_asym[kWavesPerBlock][kAsymTableLen];  // w_l a_l
 
@@ -323,17 +320,21 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
       // class boundary then pair the cheap asymptote path with one of the
       // rational paths instead of both rational paths.  Class c goes to
       // [start_c, start_c + count_c): running base per class.
+      // Each lane keeps the sorted slot of each of its items; results are
+      // written back into the slots, then stored in the original order with
+      // coalesced stores (scattered 8-byte stores into the tile had written
+      // 15-50% more bytes to HBM than the output holds).
       int base = 0, nA = 0, nAC = 0;
+      int slot[ITEMS] = {};  // items past the tile's end keep 0 and are not stored
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
           const uint64_t m = __ballot(cls[it] == c);
           if (cls[it] == c) {
-            const int pos = base + int(__builtin_amdgcn_mbcnt_hi(
-                                       uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
-            s_x[wv][pos] = xv[it];
-            s_idx[wv][pos] = it * 64 + lane;
+            slot[it] = base + int(__builtin_amdgcn_mbcnt_hi(
+                                  uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
+            s_x[wv][slot[it]] = xv[it];
           }
           base += __popcll(m);
         }
@@ -350,8 +351,14 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
           if (q < nA) acc = wsum_region_a(xq, k, wk, down, s_exp);
           else if (q < nAC) acc = wsum_region_c(xq, k, s_asym[wv]);
           else acc = wsum_region_b(xq, k, w0, up, s_exp);
-          a.out[first + s_idx[wv][q]] = acc;
+          s_x[wv][q] = acc;
         }
+      }
+      wave_sync();
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const int p = it * 64 + lane;
+        if (p < count) a.out[first + p] = s_x[wv][slot[it]];
       }
       wave_sync();
     } else {
@@ -395,9 +402,10 @@ const WsConfig kConfigs[] = {
     {&ws_kernel<2, true>, 2, 1, 12, "wave-tile128-bin-12wg"},
     {&ws_kernel<4, false>, 4, 0, 12, "wave-tile256-nobin-12wg"},
     {&ws_kernel<2, false>, 2, 0, 12, "wave-tile128-nobin-12wg"},
+    {&ws_kernel<8, true>, 8, 1, 16, "wave-tile512-bin-16wg"},
 };
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
-constexpr int kDefaultConfig = 1;
+constexpr int kDefaultConfig = 4;  // wave-tile512-bin-12wg
 
 // ---------------------------------------------------------------------------
 // Per-device state: workspace, one cached graph per configuration (so the

@@ -70,6 +70,26 @@ def test_padded_gradient_rows_and_ragged_sizes():
         assert np.all(np.abs(g - oracle.backward(x, G)) <= tol), n
 
 
+@pytest.mark.parametrize("kmax", [15, 16])
+def test_packed_rows_aligned_and_unaligned(kmax):
+    """Packed rows (ld = kmax+1) take 16-byte loads when G is 16-byte aligned
+    and 8-byte loads when it is not; both give the same gradient bit for bit.
+    Even and odd row lengths (a 16-byte unit straddles two rows when odd)."""
+    n = 64 * 37 + 29
+    x, G = workloads.backward_workload(n=n, kmax=kmax, seed=70 + kmax)
+    xt = torch.from_numpy(x).to(DEV)
+    buf = torch.zeros(n * (kmax + 1) + 1, dtype=torch.float64, device=DEV)
+    Ga = buf[:-1].view(n, kmax + 1)
+    Ga.copy_(torch.from_numpy(G))
+    Gu = buf[1:].view(n, kmax + 1)  # 8 bytes off 16-byte alignment
+    ga = boys.boys_backward(xt, Ga, kmax).cpu().numpy()
+    Gu.copy_(torch.from_numpy(G))
+    gu = boys.boys_backward(xt, Gu, kmax).cpu().numpy()
+    assert np.array_equal(ga, gu)
+    S, tol = bounds(x, G)
+    assert np.all(np.abs(ga - oracle.backward(x, G)) <= tol)
+
+
 def test_autograd_matches_kernel_and_oracle():
     x, G = workloads.backward_workload(n=5000, kmax=16, seed=3)
     xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
