@@ -13,7 +13,9 @@ Beside the headline the same JSON line carries:
                 counter summary matches the current kernel sources;
   cpu_baseline  the long-double CPU oracle on the first 2^24 arguments
                 (all host cores), with the max abs error of the GPU rows there;
-  legs          FP32 vs FP64 at kmax=16 on the same arguments, the batched
+  legs          the small mixed-argument configuration (65 536 arguments,
+                kmax=8; launch-bound), FP32 vs FP64 at kmax=16 on the same
+                arguments, the batched
                 fused consumer (8192 batches), the differentiation pass
                 (2^24 arguments, kmax=16, forward + backward), the paper's
                 own N^2 benchmark (n = 2^19, k = 12) beside its A100 time, and
@@ -22,7 +24,7 @@ Beside the headline the same JSON line carries:
                 high-order tables).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
-       [--only writeout,fp32,fused,backward,pairsum,screen,high]
+       [--only writeout,mixed,fp32,fused,backward,pairsum,screen,high]
        [--no-cpu-baseline] [--copy-probe]
 """
 from __future__ import annotations
@@ -117,6 +119,47 @@ def leg_writeout(torch, boys, workloads, steps, warmup, dev):
     log(f"write-out: {ms:.3f} ms/step, {alg_bytes / ms / 1e6:.0f} GB/s")
     return dict(x_host=x_host, x=x, out=out, ms=ms, wall=t.wall, n=n, kmax=kmax,
                 alg_bytes=alg_bytes)
+
+
+def leg_mixed(torch, boys, workloads, dev, calls=500):
+    """The small plain-FP64 configuration: 65 536 arguments in four equal
+    quarters (U[0,1], U[1,30], log-uniform [30,1e4], exact zeros or U[0,1e-6]),
+    kmax = 8.  At 5.2 MB per call it is bound by launch latency, not by HBM:
+    timed as back-to-back calls on one stream and as replays of a captured
+    graph of the same calls."""
+    kmax = 8
+    x = torch.from_numpy(workloads.mixed_arguments()).to(dev)
+    n = x.numel()
+    out = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+    for _ in range(20):
+        boys.boys_eval_f64(x, kmax, out=out)
+    with Timer(torch) as t:
+        for _ in range(calls):
+            boys.boys_eval_f64(x, kmax, out=out)
+    eager_us = t.ms * 1e3 / calls
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    per_graph = 50
+    with torch.cuda.stream(side):
+        boys.boys_eval_f64(x, kmax, out=out)
+        torch.cuda.current_stream().synchronize()
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(per_graph):
+                boys.boys_eval_f64(x, kmax, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    reps = max(1, calls // per_graph)
+    with Timer(torch) as tg:
+        for _ in range(reps):
+            g.replay()
+    graph_us = tg.ms * 1e3 / (reps * per_graph)
+    values = n * (kmax + 1)
+    log(f"mixed: {eager_us:.2f} us per call, {graph_us:.2f} us per call in a graph")
+    return {"n": n, "kmax": kmax, "us_per_call": eager_us, "us_per_call_graph": graph_us,
+            "values_per_s": values / (eager_us * 1e-6),
+            "values_per_s_graph": values / (graph_us * 1e-6),
+            "gbs_graph": n * 8 * (kmax + 2) / (graph_us * 1e3)}
 
 
 def leg_fp32(torch, boys, workloads, steps, warmup, dev, x_host=None):
@@ -339,7 +382,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="writeout,fp32,fused,backward,pairsum,screen,high")
+    ap.add_argument("--only", default="writeout,mixed,fp32,fused,backward,pairsum,screen,high")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -372,6 +415,11 @@ def main():
             extra["fp32"] = {k: v for k, v in fp32.items() if not k.startswith("_")}
         except Exception as e:  # reported, not hidden
             extra["fp32"] = {"error": str(e)}
+    if "mixed" in legs:
+        try:
+            extra["mixed"] = leg_mixed(torch, boys, workloads, dev)
+        except Exception as e:
+            extra["mixed"] = {"error": str(e)}
     if "fused" in legs:
         try:
             extra["fused"] = leg_fused(torch, boys, workloads, args.steps, args.warmup, dev)

@@ -50,6 +50,34 @@ def test_mixed_workload_kmax8():
     assert_close(run(x, 8), oracle.boys(x, 8), what="mixed kmax=8")
 
 
+def test_captured_graph_replays_match_eager():
+    """The mixed workload's calls captured in a graph (as the benchmark times
+    them): every replay, with eager work and synchronisations in between,
+    gives the eager result bit for bit."""
+    x = torch.from_numpy(workloads.mixed_arguments()).to(DEV)
+    eager = boys.boys_eval_f64(x, 8)
+    out = torch.full_like(eager, -1.0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        boys.boys_eval_f64(x, 8, out=out)
+        torch.cuda.current_stream().synchronize()
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(3):
+                boys.boys_eval_f64(x, 8, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    for rep in range(4):
+        out.fill_(-1.0)
+        boys.boys_eval_f64(x, 3)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+
+
 @pytest.mark.parametrize("kmax", range(33))
 def test_every_order(kmax):
     """Every kmax 0..32 over all three regions, the boundaries and a ragged
