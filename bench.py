@@ -387,7 +387,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); every argument "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); every argument "
               "is independent, so the path would shard by contiguous slices, but no multi-GPU "
               "run is implemented here.", file=sys.stderr)
         sys.exit(2)
