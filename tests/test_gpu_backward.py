@@ -59,22 +59,27 @@ def test_every_order(kmax):
     assert np.all(np.abs(g - oracle.backward(x, G)) <= tol)
 
 
-def test_padded_gradient_rows_and_ragged_sizes():
+@pytest.mark.parametrize("kmax", [16, 24])
+def test_padded_gradient_rows_and_ragged_sizes(kmax):
+    """Row stride kmax+5 and sizes with partial waves; kmax 24 is an order
+    whose packed rows would go to LDS by DMA, so this covers its fallback."""
     for n in (1, 63, 65, 257, 1000):
-        x, Gfull = workloads.backward_workload(n=n, kmax=20, seed=n)
-        G = Gfull[:, :17]
+        x, Gfull = workloads.backward_workload(n=n, kmax=kmax + 4, seed=n)
+        G = Gfull[:, :kmax + 1]
         xt = torch.from_numpy(x).to(DEV)
-        Gt = torch.from_numpy(Gfull).to(DEV)[:, :17]  # row stride 21
-        g = boys.boys_backward(xt, Gt, 16).cpu().numpy()
+        Gt = torch.from_numpy(Gfull).to(DEV)[:, :kmax + 1]  # row stride kmax+5
+        g = boys.boys_backward(xt, Gt, kmax).cpu().numpy()
         S, tol = bounds(x, G)
         assert np.all(np.abs(g - oracle.backward(x, G)) <= tol), n
 
 
-@pytest.mark.parametrize("kmax", [15, 16])
+@pytest.mark.parametrize("kmax", [15, 16, 18, 24, 30])
 def test_packed_rows_aligned_and_unaligned(kmax):
-    """Packed rows (ld = kmax+1) take 16-byte loads when G is 16-byte aligned
-    and 8-byte loads when it is not; both give the same gradient bit for bit.
-    Even and odd row lengths (a 16-byte unit straddles two rows when odd)."""
+    """Packed rows (ld = kmax+1) take 16-byte loads (kmax <= 16, or an even
+    row length) or LDS-DMA loads (odd row lengths from 19) when G is 16-byte
+    aligned, and 8-byte loads when it is not; all give the same gradient bit
+    for bit.  Even and odd row lengths (a 16-byte unit straddles two rows
+    when odd)."""
     n = 64 * 37 + 29
     x, G = workloads.backward_workload(n=n, kmax=kmax, seed=70 + kmax)
     xt = torch.from_numpy(x).to(DEV)
