@@ -11,7 +11,7 @@ Beside the headline the same JSON line carries:
                 average launch time from HIP events) against 8 TB/s, and the
                 HBM traffic measured by rocprofv3 counters when the committed
                 counter summary matches the current kernel sources;
-  cpu_baseline  the long-double CPU oracle on the first 2^24 arguments
+  cpu_baseline  the long-double CPU oracle on the first 2^25 arguments
                 (all host cores), with the max abs error of the GPU rows there;
   legs          the small mixed-argument configuration (65 536 arguments,
                 kmax=8; launch-bound), FP32 vs FP64 at kmax=16 on the same
@@ -330,10 +330,11 @@ def leg_high(torch, boys, workloads, steps, warmup, dev, wo=None):
 
 
 def cpu_baseline_leg(torch, wo, fp32, screen=None):
-    """The oracle on the first 2^24 write-out arguments, all host cores; the
-    GPU rows of the same arguments are compared with it on the way."""
+    """The oracle on the first 2^25 write-out arguments (half the workload,
+    about 20 thread-seconds of CPU work), all host cores; the GPU rows of the
+    same arguments are compared with it on the way."""
     import oracle
-    m = 1 << 24
+    m = 1 << 25
     chunk = 1 << 21
     threads = oracle.max_threads()
     err = 0.0
@@ -350,8 +351,8 @@ def cpu_baseline_leg(torch, wo, fp32, screen=None):
             got = screen["_out"][s:s + chunk].cpu().numpy()
             err_screen = max(err_screen, float(np.abs(got - ref).max()))
     res = {"value": m * 33 / t_cpu, "unit": "values/s", "cores": threads, "kind": "oracle",
-           "sample": f"first 2^24 of the 2^26 write-out arguments, kmax=32, long-double oracle, "
-                     f"{threads} threads, {t_cpu:.1f} s",
+           "sample": f"first 2^25 of the 2^26 write-out arguments, kmax=32, long-double oracle, "
+                     f"{threads} threads, {t_cpu:.1f} s wall ({t_cpu * threads:.0f} thread-s)",
            "gpu_max_abs_err_on_sample": err}
     if screen is not None:
         res["screen_max_abs_err_on_sample"] = err_screen
