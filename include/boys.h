@@ -59,10 +59,12 @@ enum {
 };
 
 /* Highest order of the paper's FP64 tables (every FP64 entry point), of the
- * high-order FP64 tables (boys_eval_f64 and boys_eval_f64_tol only), and of
- * the FP32 tables. */
+ * high-order FP64 tables (boys_eval_f64 and boys_eval_f64_tol), the highest
+ * kmax of boys_backward (which recomputes order kmax+1 <= 40), and the
+ * highest order of the FP32 tables. */
 #define BOYS_F64_KMAX_LIMIT 32
 #define BOYS_F64_EVAL_KMAX_LIMIT 40
+#define BOYS_F64_BACKWARD_KMAX_LIMIT 39
 #define BOYS_F32_KMAX_LIMIT 16
 
 /* Text for a status code (static storage, never NULL). */
@@ -177,10 +179,11 @@ BOYS_API int boys_weighted_sum_set_config(int config);
  *     grad_x[i] = - sum_{k=0..kmax} grad_f[i*ld_g + k] * F_{k+1}(x[i]).
  *
  * F_1..F_{kmax+1} are recomputed from x with the FP64 method at order
- * kmax+1 (nothing is saved by the forward pass).
+ * kmax+1 (nothing is saved by the forward pass): the paper's tables up to
+ * order 32, the high-order tables (as boys_eval_f64) for orders 33..40.
  *
  *   x       [n] FP64.   grad_f  row-major n x ld_g FP64, ld_g >= kmax + 1.
- *   kmax    0 <= kmax <= 31.   grad_x [n] FP64 output.
+ *   kmax    0 <= kmax <= 39.   grad_x [n] FP64 output.
  * Errors as boys_eval_f64.
  */
 BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax, int64_t ld_g,

@@ -18,6 +18,7 @@ _lib = None
 
 F64_KMAX = 32        # the paper's tables: every FP64 entry point
 F64_KMAX_EVAL = 40   # boys_eval_f64(_tol): orders 33..40 use the high-order tables
+F64_KMAX_BACKWARD = 39  # boys_backward recomputes order kmax+1 <= 40
 F32_KMAX = 16
 
 _P = ctypes.c_void_p
@@ -210,8 +211,8 @@ def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None
     n = x.numel()
     if kmax is None:
         kmax = grad_f.shape[1] - 1
-    if not 0 <= kmax <= F64_KMAX - 1:
-        raise BoysError(f"kmax must be in [0, {F64_KMAX - 1}]")
+    if not 0 <= kmax <= F64_KMAX_BACKWARD:
+        raise BoysError(f"kmax must be in [0, {F64_KMAX_BACKWARD}]")
     ld = _rows(grad_f, n, kmax + 1, torch.float64, x.device, "grad_f")
     if out is None:
         out = torch.empty_like(x)
@@ -261,8 +262,8 @@ class BoysFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, kmax: int):
-        if kmax > F64_KMAX - 1:
-            raise BoysError(f"differentiable evaluation needs kmax <= {F64_KMAX - 1}")
+        if kmax > F64_KMAX_BACKWARD:
+            raise BoysError(f"differentiable evaluation needs kmax <= {F64_KMAX_BACKWARD}")
         ctx.save_for_backward(x)
         ctx.kmax = kmax
         return boys_eval_f64(x, kmax)

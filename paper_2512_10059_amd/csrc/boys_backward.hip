@@ -6,17 +6,20 @@
 //     grad_x[i] = - sum_{k=0..kmax} G[i, k] F_{k+1}(x[i]).
 //
 // The kernel recomputes F_0..F_{kmax+1} in VGPRs with the FP64 method at
-// order kmax+1 instead of reading values saved by the forward pass: x is
-// 8 bytes per argument while the saved rows would be 8*(kmax+1).  G rows are
-// the dominant traffic (8*(kmax+1) bytes per argument); each wave reads its
-// 64 rows as one contiguous stream (16-byte loads when the rows are packed;
-// all loads issued before the evaluation, which hides their latency) into an
-// LDS slice whose row stride is padded to an odd number of doubles, so that
-// the per-lane row reads that follow are free of bank conflicts.
+// order kmax+1 (the paper's tables up to order 32, the high-order set for
+// 33..40) instead of reading values saved by the forward pass: x is 8 bytes
+// per argument while the saved rows would be 8*(kmax+1).  G rows are the
+// dominant traffic (8*(kmax+1) bytes per argument); each wave reads its 64
+// rows as one contiguous stream into an LDS slice whose row stride is an odd
+// number of doubles, so that the per-lane row reads that follow are free of
+// bank conflicts.  Packed rows come with 16-byte loads, issued before the
+// evaluation so that their latency hides behind it, or for long odd rows by
+// LDS-DMA loads that land in LDS during the evaluation.
 #include <hip/hip_runtime.h>
 
 #include <array>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "boys.h"
@@ -28,12 +31,17 @@ namespace {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restrict__ x,
-                                                          const double *__restrict__ g, int64_t n,
-                                                          int64_t ld, double *__restrict__ grad,
-                                                          int packed) {
+// Waves per workgroup: orders whose recomputation needs the high-order table
+// set (kmax+1 > 32) stage rows of 34..40 doubles, so their groups have two
+// waves (about 42 KB of LDS) instead of four (84 KB, one group per CU).
+constexpr int backward_waves(int K) { return K + 1 > kF64Kmax ? 2 : kWavesPerBlock; }
+
+template <int K, class T>
+__global__ __launch_bounds__(64 * backward_waves(K)) void backward_kernel(
+    const double *__restrict__ x, const double *__restrict__ g, int64_t n, int64_t ld,
+    double *__restrict__ grad, int packed) {
   constexpr int C = K + 1;                  // columns of G used
+  constexpr int WB = backward_waves(K);
   constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // padded LDS row stride
   // Packed rows go to LDS by LDS-DMA loads for odd row lengths from 19 on.
   // There the rows held in VGPRs across the evaluation would cap the waves
@@ -44,13 +52,13 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
   // Per-wave slice: 64 rows, plus (DMA) the slack that the last LDS-DMA
   // instruction's surplus lanes write: 128 J doubles are written in all.
   constexpr int SL = kDma ? 128 * ((32 * C + 63) / 64) : 64 * CP;
-  __shared__ __attribute__((aligned(16))) double stage[kWavesPerBlock * SL];
+  __shared__ __attribute__((aligned(16))) double stage[WB * SL];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double *slice = stage + wave * SL;
 
-  for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
-    const int64_t row0 = blk * kBlock + int64_t(wave) * 64;
+  for (int64_t blk = blockIdx.x; blk * (64 * WB) < n; blk += gridDim.x) {
+    const int64_t row0 = blk * (64 * WB) + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     const int rows = n - row0 < 64 ? int(n - row0 > 0 ? n - row0 : 0) : 64;
     double F[C + 1];
@@ -78,14 +86,40 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
               (const __attribute__((address_space(1))) void *)(src + (u < U ? u : U - 1)),
               (__attribute__((address_space(3))) void *)(slice + 128 * jj), 16, 0, 0);
         }
-        boys_f64<K + 1>(xv, F);
+        boys_f64<K + 1, T>(xv, F);
         __builtin_amdgcn_s_waitcnt(0);  // the LDS-DMA loads have landed
       } else {
         // Strided rows or a partial wave: evaluate first, then copy the rows
         // to LDS element by element (64 consecutive elements per load when
         // the rows are packed), so that the register budget stays that of
         // the DMA path.
-        boys_f64<K + 1>(i < n ? x[i] : 0.0, F);
+        boys_f64<K + 1, T>(i < n ? x[i] : 0.0, F);
+#pragma unroll 4
+        for (int e = lane; e < rows * C; e += 64) {
+          const int r = e / C, c = e - r * C;
+          slice[r * CP + c] = g[(row0 + r) * ld + c];
+        }
+      }
+    } else if constexpr (C > kF64Kmax) {
+      // Even row lengths of the high orders: rows held across the evaluation
+      // would take over 300 VGPRs, so evaluate first, then read the rows
+      // (16-byte loads when packed, else element by element).
+      boys_f64<K + 1, T>(i < n ? x[i] : 0.0, F);
+      if (rows == 64 && packed) {
+        constexpr int U = 32 * C;
+        constexpr int J = (U + 63) / 64;
+        const d2 *src = reinterpret_cast<const d2 *>(g + row0 * C);
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+          const int u = lane + 64 * jj;
+          if (u < U) {
+            const d2 v = __builtin_nontemporal_load(src + u);
+            const int e = 2 * u, r = e / C, c = e - r * C;  // C even: no straddle
+            slice[r * CP + c] = v.x;
+            slice[r * CP + c + 1] = v.y;
+          }
+        }
+      } else {
 #pragma unroll 4
         for (int e = lane; e < rows * C; e += 64) {
           const int r = e / C, c = e - r * C;
@@ -107,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
         const int u = lane + 64 * jj;
         gv[jj] = __builtin_nontemporal_load(src + (u < U ? u : U - 1));
       }
-      boys_f64<K + 1>(x[i], F);
+      boys_f64<K + 1, T>(x[i], F);
 #pragma unroll
       for (int jj = 0; jj < J; ++jj) {
         const int u = lane + 64 * jj;
@@ -128,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
         const int e = lane + 64 * jj, r = e / C, c = e - r * C;
         gv[jj] = __builtin_nontemporal_load(g + (row0 + r) * ld + c);
       }
-      boys_f64<K + 1>(x[i], F);
+      boys_f64<K + 1, T>(x[i], F);
 #pragma unroll
       for (int jj = 0; jj < C; ++jj) {
         const int e = lane + 64 * jj, r = e / C, c = e - r * C;
@@ -139,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
         const int r = e / C, c = e - r * C;
         slice[r * CP + c] = g[(row0 + r) * ld + c];
       }
-      boys_f64<K + 1>(i < n ? x[i] : 0.0, F);
+      boys_f64<K + 1, T>(i < n ? x[i] : 0.0, F);
     }
     __syncthreads();
     if (i < n) {
@@ -154,11 +188,17 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(const double *__restri
 
 using BackwardKernel = void (*)(const double *, const double *, int64_t, int64_t, double *, int);
 
+// kmax 0..31 recompute orders up to 32 with the paper's tables; kmax 32..39
+// recompute orders 33..40 with the high-order set.
+constexpr int kBackwardKmax = kHighKmax - 1;
+template <int K>
+using BackwardSet = std::conditional_t<(K + 1 > kF64Kmax), HighTables, PaperTables>;
 template <std::size_t... K>
 constexpr auto make_table(std::index_sequence<K...>) {
-  return std::array<BackwardKernel, sizeof...(K)>{{&backward_kernel<int(K)>...}};
+  return std::array<BackwardKernel, sizeof...(K)>{
+      {&backward_kernel<int(K), BackwardSet<int(K)>>...}};
 }
-constexpr auto kBackwardTable = make_table(std::make_index_sequence<kF64Kmax>{});
+constexpr auto kBackwardTable = make_table(std::make_index_sequence<kBackwardKmax + 1>{});
 
 }  // namespace
 }  // namespace boys
@@ -166,7 +206,7 @@ constexpr auto kBackwardTable = make_table(std::make_index_sequence<kF64Kmax>{})
 extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax,
                              int64_t ld_g, double *grad_x, hipStream_t stream) {
   using namespace boys;
-  if (n < 0 || kmax < 0 || kmax > kF64Kmax - 1 || ld_g < kmax + 1) return BOYS_EINVAL;
+  if (n < 0 || kmax < 0 || kmax > kBackwardKmax || ld_g < kmax + 1) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !grad_f || !grad_x) return BOYS_EINVAL;
   if (n - 1 > (INT64_MAX / 8 - (kmax + 1)) / ld_g) return BOYS_EINVAL;
@@ -175,10 +215,11 @@ extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, i
     return BOYS_EINVAL;
   if (int st = check_device()) return st;
 
-  int64_t blocks = (n + kBlock - 1) / kBlock;
+  const int block = 64 * backward_waves(kmax);
+  int64_t blocks = (n + block - 1) / block;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
   const int packed = ld_g == kmax + 1 && (reinterpret_cast<uintptr_t>(grad_f) & 15) == 0;
-  hipLaunchKernelGGL(kBackwardTable[kmax], dim3(unsigned(blocks)), dim3(kBlock), 0, stream, x,
+  hipLaunchKernelGGL(kBackwardTable[kmax], dim3(unsigned(blocks)), dim3(block), 0, stream, x,
                      grad_f, n, ld_g, grad_x, packed);
   return hip_status(hipGetLastError());
 }

@@ -68,7 +68,7 @@ def test_argument_errors_without_gpu(lib):
     assert g(dummy, 0, 16, None, 17, None) == 0
     b = lib.boys_backward
     b.argtypes = [P, P, I64, I, I64, P, P]
-    assert b(dummy, dummy, 10, 32, 33, dummy, None) == EINVAL  # needs F_{kmax+1}
+    assert b(dummy, dummy, 10, 40, 41, dummy, None) == EINVAL  # needs F_41
     assert b(dummy, dummy, 10, 5, 5, dummy, None) == EINVAL    # ld_g < kmax+1
     assert b(dummy, dummy, 0, 5, 6, dummy, None) == 0
     w = lib.boys_weighted_sum

@@ -51,8 +51,11 @@ def test_gradient_vs_oracle_and_central_difference():
     assert strict > 0.99, f"only {strict:.4f} within 1e-10 S"
 
 
-@pytest.mark.parametrize("kmax", [0, 1, 5, 8, 15, 16, 24, 31])
+@pytest.mark.parametrize("kmax", [0, 1, 5, 8, 15, 16, 24, 31, 32, 33, 36, 38, 39])
 def test_every_order(kmax):
+    """Orders up to 31 recompute F_{kmax+1} with the paper's tables, 32..39
+    with the high-order set; even and odd row lengths, full and partial
+    waves."""
     x, G = workloads.backward_workload(n=3000, kmax=kmax, seed=40 + kmax)
     g = gpu_backward(x, G)
     S, tol = bounds(x, G)
@@ -95,6 +98,19 @@ def test_packed_rows_aligned_and_unaligned(kmax):
     assert np.all(np.abs(ga - oracle.backward(x, G)) <= tol)
 
 
+def test_autograd_at_high_orders():
+    """BoysFunction at kmax 36 and 39 (forward and backward through the
+    high-order tables) against the oracle."""
+    for kmax in (36, 39):
+        x, G = workloads.backward_workload(n=3000, kmax=kmax, seed=80 + kmax)
+        xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+        F = boys.BoysFunction.apply(xt, kmax)
+        F.backward(torch.from_numpy(G).to(DEV))
+        S, tol = bounds(x, G)
+        assert np.all(np.abs(xt.grad.cpu().numpy() - oracle.backward(x, G)) <= tol), kmax
+        assert np.abs(F.detach().cpu().numpy() - oracle.boys(x, kmax)).max() <= EPS_TOL
+
+
 def test_autograd_matches_kernel_and_oracle():
     x, G = workloads.backward_workload(n=5000, kmax=16, seed=3)
     xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
@@ -117,7 +133,7 @@ def test_empty_and_invalid():
     assert boys.boys_backward(x, G, 16).numel() == 0
     x = torch.ones(4, dtype=torch.float64, device=DEV)
     with pytest.raises(boys.BoysError):
-        boys.boys_backward(x, torch.ones((4, 33), dtype=torch.float64, device=DEV), 32)
+        boys.boys_backward(x, torch.ones((4, 41), dtype=torch.float64, device=DEV), 40)
     with pytest.raises(boys.BoysError):
         boys.boys_backward(x, torch.ones((4, 3), dtype=torch.float64, device=DEV), 5)
 
