@@ -17,7 +17,8 @@ Beside the headline the same JSON line carries:
                 kmax=8; launch-bound), FP32 vs FP64 at kmax=16 on the same
                 arguments, the batched
                 fused consumer (8192 batches), the differentiation pass
-                (2^24 arguments, kmax=16, forward + backward), the paper's
+                (2^24 arguments, kmax=16, forward + backward; backward also
+                at kmax=30), the paper's
                 own N^2 benchmark (n = 2^19, k = 12) beside its A100 time, and
                 the screening table set (eps_tol = 1e-10) on the write-out
                 and pair-sum workloads, and the write-out at kmax = 40 (the
@@ -242,10 +243,25 @@ def leg_backward(torch, boys, workloads, steps, warmup, dev):
         for _ in range(steps):
             boys.boys_backward(x, G, kmax, out=g)
     fms, bms = tf.ms / steps, tb.ms / steps
-    log(f"backward: forward {fms:.3f} ms, backward {bms:.3f} ms")
+    del G, F
+    # The same pass at kmax = 30, where the gradient rows reach LDS by
+    # LDS-DMA loads during the evaluation.
+    k_hi = 30
+    _, G_hi = workloads.backward_workload(n=n, kmax=k_hi)
+    G = torch.from_numpy(G_hi).to(dev)
+    del G_hi
+    for _ in range(warmup):
+        boys.boys_backward(x, G, k_hi, out=g)
+    with Timer(torch) as th:
+        for _ in range(steps):
+            boys.boys_backward(x, G, k_hi, out=g)
+    hms = th.ms / steps
+    del G
+    log(f"backward: forward {fms:.3f} ms, backward {bms:.3f} ms, backward at kmax {k_hi} {hms:.3f} ms")
     return {"n": n, "kmax": kmax, "ms_forward": fms, "ms_backward": bms,
             "gbs_forward": n * 8 * (kmax + 2) / (fms * 1e6),
-            "gbs_backward": n * 8 * (kmax + 3) / (bms * 1e6)}
+            "gbs_backward": n * 8 * (kmax + 3) / (bms * 1e6),
+            "ms_backward_kmax30": hms, "gbs_backward_kmax30": n * 8 * (k_hi + 3) / (hms * 1e6)}
 
 
 def leg_pairsum(torch, boys, workloads, steps, dev):
