@@ -212,14 +212,22 @@ def leg_fused(torch, boys, workloads, steps, warmup, dev):
         for _ in range(steps):
             boys.boys_weighted_sum(*args, out=out)
     ms = tm.ms / steps
+    # The same calls with the screening tables (eps_tol = 1e-10), same
+    # configuration.
+    for _ in range(warmup):
+        boys.boys_weighted_sum(*args, out=out, tol=1e-10)
+    with Timer(torch) as ts:
+        for _ in range(steps):
+            boys.boys_weighted_sum(*args, out=out, tol=1e-10)
+    ms_screen = ts.ms / steps
     kk = np.repeat(bt.batch_kmax.astype(np.int64), bt.batch_n.astype(np.int64))
     values = int((kk + 1).sum())
     from paper_2512_10059_amd.tables import f64_region_a_degrees
     flops = float(algorithmic_flops(bt.x, kk, f64_region_a_degrees()))
     nbytes = bt.x.size * 16 + bt.w.size * 8 + bt.batch_n.size * 24
-    log(f"fused: {ms:.3f} ms, config {name}")
+    log(f"fused: {ms:.3f} ms, config {name}; screening tables {ms_screen:.3f} ms")
     return {"nbatch": int(bt.batch_n.size), "arguments": int(bt.x.size), "values": values,
-            "ms": ms, "config": name, "tune_ms": tune_ms,
+            "ms": ms, "config": name, "tune_ms": tune_ms, "ms_screen_1e-10": ms_screen,
             "values_per_s": values / (ms * 1e-3),
             "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
             "fp64_peak_frac_algorithmic": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,

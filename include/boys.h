@@ -154,6 +154,19 @@ BOYS_API int boys_weighted_sum(const double *x, const int64_t *batch_off, const 
                       int32_t nbatch, double *out, hipStream_t stream);
 
 /*
+ * boys_weighted_sum with the table set chosen by tol as in boys_eval_f64_tol:
+ * tol >= 1e-10 takes the screening set (per argument |error| <= 1e-10
+ * sum_l |w_l| plus rounding), 5e-14 <= tol < 1e-10 the paper's tables (the
+ * same result as boys_weighted_sum, bit for bit).  The configuration chosen
+ * by boys_tune_weighted_sum serves both sets.  Errors: as boys_weighted_sum,
+ * and BOYS_EINVAL for tol < 5e-14 or NaN.
+ */
+BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
+                                   const int32_t *batch_n, const int32_t *batch_kmax,
+                                   const double *w, const int64_t *w_off, int32_t nbatch,
+                                   double tol, double *out, hipStream_t stream);
+
+/*
  * Times every tile/unroll configuration of the persistent kernel on these
  * arguments (each run writes out), keeps the fastest for later
  * boys_weighted_sum calls on this device, and reports it.  Synchronises

@@ -33,6 +33,7 @@ _SIGNATURES = {
     "boys_eval_f64_tol": ([_P, _I64, _INT, ctypes.c_double, _P, _I64, _P], _INT),
     "boys_eval_f32": ([_P, _I64, _INT, _P, _I64, _P], _INT),
     "boys_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P], _INT),
+    "boys_weighted_sum_tol": ([_P, _P, _P, _P, _P, _P, _I32, ctypes.c_double, _P, _P], _INT),
     "boys_tune_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P,
                                 ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_float)], _INT),
     "boys_weighted_sum_num_configs": ([], _INT),
@@ -161,16 +162,24 @@ def _batch_args(x, batch_off, batch_n, batch_kmax, w, w_off):
     return nb
 
 
-def boys_weighted_sum(x, batch_off, batch_n, batch_kmax, w, w_off, out=None) -> torch.Tensor:
-    """out[i] = sum_l w[w_off[b]+l] F_l(x[i]) for every argument i of batch b."""
+def boys_weighted_sum(x, batch_off, batch_n, batch_kmax, w, w_off, out=None,
+                      tol=None) -> torch.Tensor:
+    """out[i] = sum_l w[w_off[b]+l] F_l(x[i]) for every argument i of batch b.
+
+    tol: None for the paper's tables, else as boys_eval_f64_tol (1e-10 or
+    more takes the screening tables)."""
     nb = _batch_args(x, batch_off, batch_n, batch_kmax, w, w_off)
     if out is None:
         out = torch.zeros_like(x)
     _vector(out, torch.float64, "out")
+    args = (_ptr(x), _ptr(batch_off), _ptr(batch_n), _ptr(batch_kmax), _ptr(w), _ptr(w_off), nb)
     with torch.cuda.device(x.device):
-        _check(lib().boys_weighted_sum(_ptr(x), _ptr(batch_off), _ptr(batch_n), _ptr(batch_kmax),
-                                       _ptr(w), _ptr(w_off), nb, _ptr(out), _stream(x.device)),
-               "boys_weighted_sum")
+        if tol is None:
+            _check(lib().boys_weighted_sum(*args, _ptr(out), _stream(x.device)),
+                   "boys_weighted_sum")
+        else:
+            _check(lib().boys_weighted_sum_tol(*args, float(tol), _ptr(out), _stream(x.device)),
+                   "boys_weighted_sum_tol")
     return out
 
 

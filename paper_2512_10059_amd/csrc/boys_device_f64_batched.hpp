@@ -3,6 +3,8 @@
 // boys_device_f64.hpp.
 #pragma once
 
+#include <type_traits>
+
 #include "boys_device_f64.hpp"
 #include "boys_consumer_tables.h"
 
@@ -106,42 +108,62 @@ __device__ __forceinline__ double rational_b_t(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// r_{A,k} for a runtime, wave-uniform k (the batched consumer).  The rows
-// live in a constant-memory table read with wide scalar loads at the
-// address of row k, instead of a 33-way branch to literal-coded passes.  Rows
-// are stored for fixed-length Horner passes: P with zeros above n_k, Q monic
-// with its leading 1 at m_k and zeros above.  The extra leading steps compute
-// 0*x + 0 = 0, then 0*x + 1 = 1, then 1*x + q_{m-1}, which is the
+// r_{A,k} for a runtime, wave-uniform k (the batched consumer).  The rows of
+// a table set live in a constant-memory table read with wide scalar loads at
+// the address of row k, instead of a 33-way branch to literal-coded passes.
+// Rows are stored for fixed-length Horner passes: P with zeros above n_k, Q
+// monic with its leading 1 at m_k and zeros above.  The extra leading steps
+// compute 0*x + 0 = 0, then 0*x + 1 = 1, then 1*x + q_{m-1}, which is the
 // x + q_{m-1} of the exact-length pass rounded once, so the result is the
-// same to the last bit.  Orders k >= kSplitK all have (n, m) <= (8, 9); lower
-// orders take (8, 13).
-constexpr int kPadN = BOYS_RA_NMAX;
-constexpr int kPadM = BOYS_RA_MMAX;
+// same to the last bit.  Two pass lengths cover the orders: the largest
+// (n, m) over all orders for k < kSplitK, and the largest over k >= kSplitK
+// for the rest ((8, 13) and (8, 9) for the paper's tables, (7, 10) and
+// (7, 7) for the screening set).
 constexpr int kSplitK = 8;
-constexpr int kHiM = 9;
 
-struct RaRows {
-  double p[kF64Kmax + 1][kPadN + 1];
-  double q[kF64Kmax + 1][kPadM + 1];
+template <class T>
+constexpr int max_ra_n() {
+  int v = 0;
+  for (int k = 0; k <= kF64Kmax; ++k) v = T::ra_n[k] > v ? T::ra_n[k] : v;
+  return v;
+}
+template <class T>
+constexpr int max_ra_m(int from) {
+  int v = 0;
+  for (int k = from; k <= kF64Kmax; ++k) v = T::ra_m[k] > v ? T::ra_m[k] : v;
+  return v;
+}
+
+template <class T>
+struct RtRows {
+  static constexpr int pad_n = max_ra_n<T>();
+  static constexpr int pad_m = max_ra_m<T>(0);
+  static constexpr int hi_m = max_ra_m<T>(kSplitK);
+  double p[kF64Kmax + 1][pad_n + 1];
+  double q[kF64Kmax + 1][pad_m + 1];
 };
 
-constexpr RaRows make_ra_rows() {
-  RaRows t{};
+template <class T>
+constexpr RtRows<T> make_rt_rows() {
+  RtRows<T> t{};
   for (int k = 0; k <= kF64Kmax; ++k) {
-    for (int i = 0; i <= kRaN[k]; ++i) t.p[k][i] = kRaP[k][i];
-    for (int i = 0; i <= kRaM[k]; ++i) t.q[k][i] = kRaQ[k][i];
+    for (int i = 0; i <= T::ra_n[k]; ++i) t.p[k][i] = T::ra_p[k][i];
+    for (int i = 0; i <= T::ra_m[k]; ++i) t.q[k][i] = T::ra_q[k][i];
   }
   return t;
 }
 
-constexpr bool split_holds() {
-  for (int k = kSplitK; k <= kF64Kmax; ++k)
-    if (kRaN[k] > kPadN || kRaM[k] > kHiM) return false;
-  return true;
-}
-static_assert(split_holds(), "orders >= kSplitK must fit the (8, 9) pass");
+static_assert(RtRows<PaperTables>::pad_n == BOYS_RA_NMAX && RtRows<PaperTables>::pad_m == BOYS_RA_MMAX &&
+                  RtRows<PaperTables>::hi_m == 9,
+              "the paper's rows take the (8, 13) and (8, 9) passes");
+static __constant__ const RtRows<PaperTables> kRaRows = make_rt_rows<PaperTables>();
+static __constant__ const RtRows<ScreenTables> kRaRowsScreen = make_rt_rows<ScreenTables>();
 
-static __constant__ const RaRows kRaRows = make_ra_rows();
+template <class T>
+__device__ __forceinline__ const RtRows<T> &rt_rows() {
+  if constexpr (std::is_same_v<T, ScreenTables>) return kRaRowsScreen;
+  else return kRaRows;
+}
 
 // p(x)/q(x) by Horner passes of NP and NQ steps over P[0..NP], Q[0..NQ].
 template <int NP, int NQ>
@@ -155,11 +177,14 @@ __device__ __forceinline__ double rational_loaded(double x, const double *P, con
   return p / q;
 }
 
+template <class T = PaperTables>
 __device__ __forceinline__ double rational_a_rt(double x, int k) {
-  const double *P = kRaRows.p[k];
-  const double *Q = kRaRows.q[k];
-  if (k < kSplitK) return rational_loaded<kPadN, kPadM>(x, P, Q);
-  return rational_loaded<kPadN, kHiM>(x, P, Q);
+  using R = RtRows<T>;
+  const R &rows = rt_rows<T>();
+  const double *P = rows.p[k];
+  const double *Q = rows.q[k];
+  if (k < kSplitK) return rational_loaded<R::pad_n, R::pad_m>(x, P, Q);
+  return rational_loaded<R::pad_n, R::hi_m>(x, P, Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,11 +220,12 @@ constexpr int kPad = kChunk;
 constexpr int kTableLen = kF64Kmax + 1 + 2 * kPad;
 
 // Region A: r_{A,k}, then F_l = (2x F_{l+1} + e^-x) * (1/(2l+1)) downwards.
+template <class T = PaperTables>
 __device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down,
                                                 const double *s_exp) {
   const double e = exp_neg(x, s_exp);
   const double two_x = x + x;
-  double F = rational_a_rt(x, k);
+  double F = rational_a_rt<T>(x, k);
   double acc = wk * F;
   for (int l0 = k - 1; l0 >= 0; l0 -= kChunk) {
     wpair t[kChunk];
@@ -215,11 +241,12 @@ __device__ __forceinline__ double wsum_region_a(double x, int k, double wk, cons
 }
 
 // Region B: r_B, then F_{l+1} = ((2l+1) F_l - e^-x) / (2x) upwards.
+template <class T = PaperTables>
 __device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up,
                                                 const double *s_exp) {
   const double e = exp_neg(x, s_exp);
   const double inv_2x = 0.5 / x;
-  double F = rational_b_t<PaperTables>(x);
+  double F = rational_b_t<T>(x);
   double acc = w0 * F;
   for (int l0 = 0; l0 < k; l0 += kChunk) {
     wpair t[kChunk];

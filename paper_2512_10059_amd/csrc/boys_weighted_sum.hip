@@ -238,7 +238,7 @@ __device__ __forceinline__ void wave_sync() {
 // region (ballots and lane prefix counts, no atomics) into its LDS slice, so
 // each 64-lane pass over the sorted tile runs a single region path except at
 // the two region boundaries.  No workgroup barrier follows the set-up.
-template <int ITEMS, bool BIN>
+template <int ITEMS, bool BIN, class TS>
 __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   static_assert((ITEMS & (ITEMS - 1)) == 0, "tiles are powers of two: the scan counts them by shifts");
   constexpr int T = 64 * ITEMS;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
         const int p = it * 64 + lane;
-        cls[it] = p >= count ? 3 : (xv[it] < kX0 ? 0 : (region_c(xv[it]) ? 1 : 2));
+        cls[it] = p >= count ? 3 : (xv[it] < TS::x0 ? 0 : (region_c<TS>(xv[it]) ? 1 : 2));
       }
       // Classes in the order A, C, B: the two 64-lane passes that straddle a
       // class boundary then pair the cheap asymptote path with one of the
@@ -348,9 +348,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (q < count) {
           const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a(xq, k, wk, down, s_exp);
+          if (q < nA) acc = wsum_region_a<TS>(xq, k, wk, down, s_exp);
           else if (q < nAC) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b(xq, k, w0, up, s_exp);
+          else acc = wsum_region_b<TS>(xq, k, w0, up, s_exp);
           s_x[wv][q] = acc;
         }
       }
@@ -369,9 +369,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < kX0) acc = wsum_region_a(xq, k, wk, down, s_exp);
-          else if (region_c(xq)) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b(xq, k, w0, up, s_exp);
+          if (xq < TS::x0) acc = wsum_region_a<TS>(xq, k, wk, down, s_exp);
+          else if (region_c<TS>(xq)) acc = wsum_region_c(xq, k, s_asym[wv]);
+          else acc = wsum_region_b<TS>(xq, k, w0, up, s_exp);
           a.out[first + p] = acc;
         }
       }
@@ -386,24 +386,28 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
 using WsKernel = void (*)(WsArgs);
 
 struct WsConfig {
-  WsKernel kernel;
-  int items;        // arguments per lane per tile (tile = 64 * items)
-  int bin;          // region binning in LDS
+  WsKernel kernel;         // the paper's tables
+  WsKernel kernel_screen;  // the screening tables (eps_tol = 1e-10)
+  int items;               // arguments per lane per tile (tile = 64 * items)
+  int bin;                 // region binning in LDS
   int blocks_per_cu;
   const char *name;
 };
 
+#define BOYS_WS_CONFIG(ITEMS, BIN, WG, NAME) \
+  {&ws_kernel<ITEMS, BIN, PaperTables>, &ws_kernel<ITEMS, BIN, ScreenTables>, ITEMS, BIN, WG, NAME}
 const WsConfig kConfigs[] = {
-    {&ws_kernel<4, true>, 4, 1, 8, "wave-tile256-bin-8wg"},
-    {&ws_kernel<4, true>, 4, 1, 12, "wave-tile256-bin-12wg"},
-    {&ws_kernel<4, true>, 4, 1, 16, "wave-tile256-bin-16wg"},
-    {&ws_kernel<8, true>, 8, 1, 8, "wave-tile512-bin-8wg"},
-    {&ws_kernel<8, true>, 8, 1, 12, "wave-tile512-bin-12wg"},
-    {&ws_kernel<2, true>, 2, 1, 12, "wave-tile128-bin-12wg"},
-    {&ws_kernel<4, false>, 4, 0, 12, "wave-tile256-nobin-12wg"},
-    {&ws_kernel<2, false>, 2, 0, 12, "wave-tile128-nobin-12wg"},
-    {&ws_kernel<8, true>, 8, 1, 16, "wave-tile512-bin-16wg"},
+    BOYS_WS_CONFIG(4, true, 8, "wave-tile256-bin-8wg"),
+    BOYS_WS_CONFIG(4, true, 12, "wave-tile256-bin-12wg"),
+    BOYS_WS_CONFIG(4, true, 16, "wave-tile256-bin-16wg"),
+    BOYS_WS_CONFIG(8, true, 8, "wave-tile512-bin-8wg"),
+    BOYS_WS_CONFIG(8, true, 12, "wave-tile512-bin-12wg"),
+    BOYS_WS_CONFIG(2, true, 12, "wave-tile128-bin-12wg"),
+    BOYS_WS_CONFIG(4, false, 12, "wave-tile256-nobin-12wg"),
+    BOYS_WS_CONFIG(2, false, 12, "wave-tile128-nobin-12wg"),
+    BOYS_WS_CONFIG(8, true, 16, "wave-tile512-bin-16wg"),
 };
+#undef BOYS_WS_CONFIG
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
 constexpr int kDefaultConfig = 4;  // wave-tile512-bin-12wg
 
@@ -415,6 +419,7 @@ struct GraphKey {
   const void *ptrs[7];
   int32_t nbatch;
   int config;
+  int set;  // 0: the paper's tables, 1: the screening tables
   const void *ws;
   bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -430,12 +435,13 @@ struct DeviceState {
   std::mutex mu;
   int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
   int64_t ws_cap = 0;
-  GraphSlot slot[kNumConfigs];
-  int config = -1;  // -1: not chosen yet
+  GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
+  int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
   bool has_graphs() const {
-    for (const GraphSlot &g : slot)
-      if (g.exec || g.graph) return true;
+    for (const auto &row : slot)
+      for (const GraphSlot &g : row)
+        if (g.exec || g.graph) return true;
     return false;
   }
 };
@@ -452,7 +458,8 @@ void drop_slot(GraphSlot &g) {
 }
 
 void drop_graphs(DeviceState &s) {
-  for (GraphSlot &g : s.slot) drop_slot(g);
+  for (auto &row : s.slot)
+    for (GraphSlot &g : row) drop_slot(g);
 }
 
 // Configuration from the tuning cache file named by BOYS_TUNE_CACHE (lines
@@ -517,15 +524,16 @@ int ensure_workspace(DeviceState &s, int32_t nbatch) {
 }
 
 // Builds (or reuses) the graph {scan -> persistent kernel} for this call.
-int prepare_graph(DeviceState &s, const Call &c, int cfg) {
+int prepare_graph(DeviceState &s, const Call &c, int cfg, int set) {
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   const void *p[7] = {c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out};
   std::memcpy(key.ptrs, p, sizeof(p));
   key.nbatch = c.nbatch;
   key.config = cfg;
+  key.set = set;
   key.ws = s.ws;
-  GraphSlot &g = s.slot[cfg];
+  GraphSlot &g = s.slot[set][cfg];
   if (g.has_key && g.exec && key == g.key) return BOYS_OK;
   drop_slot(g);
 
@@ -552,7 +560,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg) {
   WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
   void *main_args[] = {&args};
   hipKernelNodeParams mp = {};
-  mp.func = reinterpret_cast<void *>(conf.kernel);
+  mp.func = reinterpret_cast<void *>(set ? conf.kernel_screen : conf.kernel);
   mp.gridDim = dim3(unsigned(s.cus * conf.blocks_per_cu));
   mp.blockDim = dim3(kBlock);
   mp.sharedMemBytes = 0;
@@ -587,15 +595,27 @@ int device_state(DeviceState **out) {
   return BOYS_OK;
 }
 
-// Enqueues one evaluation with configuration cfg (state lock held).
-int launch(DeviceState &s, const Call &c, int cfg, hipStream_t stream) {
+// Enqueues one evaluation with configuration cfg and table set `set` (state
+// lock held).
+int launch(DeviceState &s, const Call &c, int cfg, int set, hipStream_t stream) {
   if (int st = ensure_workspace(s, c.nbatch)) return st;
-  if (int st = prepare_graph(s, c, cfg)) {
-    drop_slot(s.slot[cfg]);
+  if (int st = prepare_graph(s, c, cfg, set)) {
+    drop_slot(s.slot[set][cfg]);
     return st;
   }
-  BOYS_TRY_HIP(hipGraphLaunch(s.slot[cfg].exec, stream));
+  BOYS_TRY_HIP(hipGraphLaunch(s.slot[set][cfg].exec, stream));
   return BOYS_OK;
+}
+
+int weighted_sum_with_set(const Call &c, int set, hipStream_t stream) {
+  if (int st = validate(c)) return st;
+  if (c.nbatch == 0) return BOYS_OK;
+  if (int st = check_device()) return st;
+  DeviceState *s = nullptr;
+  if (int st = device_state(&s)) return st;
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (s->config < 0) s->config = cached_config(c.nbatch);
+  return launch(*s, c, s->config, set, stream);
 }
 
 }  // namespace
@@ -607,15 +627,18 @@ int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *
                       const int32_t *batch_kmax, const double *w, const int64_t *w_off,
                       int32_t nbatch, double *out, hipStream_t stream) {
   using namespace boys;
-  const Call c{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out};
-  if (int st = validate(c)) return st;
-  if (nbatch == 0) return BOYS_OK;
-  if (int st = check_device()) return st;
-  DeviceState *s = nullptr;
-  if (int st = device_state(&s)) return st;
-  std::lock_guard<std::mutex> lock(s->mu);
-  if (s->config < 0) s->config = cached_config(nbatch);
-  return launch(*s, c, s->config, stream);
+  return weighted_sum_with_set(Call{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out}, 0,
+                               stream);
+}
+
+int boys_weighted_sum_tol(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                          const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                          int32_t nbatch, double tol, double *out, hipStream_t stream) {
+  using namespace boys;
+  const int set = table_set_for(kF64Kmax, tol);
+  if (set < 0) return BOYS_EINVAL;
+  return weighted_sum_with_set(Call{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out},
+                               set == kSetScreen ? 1 : 0, stream);
 }
 
 int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
@@ -644,12 +667,12 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   float tmin[kNumConfigs] = {};
   int st = BOYS_OK;
   for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg)
-    st = launch(*s, c, cfg, stream);  // warm-up (and graph build)
+    st = launch(*s, c, cfg, 0, stream);  // warm-up (and graph build)
   for (int r = 0; r < kRounds && st == BOYS_OK; ++r) {
     for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg) {
       float t = 0.0f;
       if ((st = hip_status(hipEventRecord(e0, stream)))) break;
-      if ((st = launch(*s, c, cfg, stream))) break;
+      if ((st = launch(*s, c, cfg, 0, stream))) break;
       if ((st = hip_status(hipEventRecord(e1, stream)))) break;
       if ((st = hip_status(hipEventSynchronize(e1)))) break;
       if ((st = hip_status(hipEventElapsedTime(&t, e0, e1)))) break;
@@ -665,7 +688,7 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   if (st != BOYS_OK) return st;
   s->config = best;
   store_config(nbatch, best);
-  if ((st = launch(*s, c, best, stream))) return st;  // leaves the graph of the winner cached
+  if ((st = launch(*s, c, best, 0, stream))) return st;  // leaves the graph of the winner cached
   if (best_config) *best_config = best;
   if (best_ms) *best_ms = best_t;
   return BOYS_OK;

@@ -100,3 +100,8 @@ def test_tolerance_argument_errors_without_gpu(lib):
     assert p(dummy, dummy, 10, dummy, 4, 1e-15, dummy, None) == EINVAL
     assert p(dummy, dummy, 10, dummy, 4, float("nan"), dummy, None) == EINVAL
     assert p(dummy, dummy, 0, dummy, 4, 1e-10, dummy, None) == 0
+    w = lib.boys_weighted_sum_tol
+    w.argtypes = [P] * 6 + [ctypes.c_int32, D, P, P]
+    for tol in (1e-15, float("nan")):
+        assert w(*([dummy] * 6), 3, tol, dummy, None) == EINVAL
+    assert w(*([None] * 6), 0, 1e-10, None, None) == 0

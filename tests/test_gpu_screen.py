@@ -1,5 +1,6 @@
-"""The screening table set (eps_tol = 1e-10) through boys_eval_f64_tol and
-boys_pairsum_tol on the GPU, against the long-double oracle.
+"""The screening table set (eps_tol = 1e-10) through boys_eval_f64_tol,
+boys_pairsum_tol and boys_weighted_sum_tol on the GPU, against the
+long-double oracle.
 
 Bar: 1e-10 absolute per F_k (the set's guarantee; the FP64 rounding of the
 evaluation adds ~1e-16), and for the pair sums 1e-10 sum_l |c_l| sum_j |y_j|
@@ -112,3 +113,77 @@ def test_pairsum_paper_tolerance_is_boys_pairsum():
     a = boys.boys_pairsum(dev(x), dev(y), c).cpu().numpy()
     b = boys.boys_pairsum(dev(x), dev(y), c, tol=5e-14).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+# --- the batched consumer (boys_weighted_sum_tol) -----------------------------
+
+def _batches(seed, nbatch=240):
+    """Small batches of every order 0..32 over the write-out distribution,
+    with empty batches and the region boundaries of both sets planted."""
+    bt = workloads.batched_workload(nbatch=nbatch, seed=seed, mean_size=300.0, sigma=1.2,
+                                    max_size=4000)
+    bt.batch_n[5::41] = 0
+    edges = edge_arguments()
+    b = int(np.argmax(bt.batch_n))
+    assert bt.batch_n[b] >= edges.size
+    bt.x[int(bt.batch_off[b]):int(bt.batch_off[b]) + edges.size] = edges
+    return bt
+
+
+def _ws(bt, tol=None, out=None):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return boys.boys_weighted_sum(t(bt.x), t(bt.batch_off), t(bt.batch_n), t(bt.batch_kmax),
+                                  t(bt.w), t(bt.w_off), out=out, tol=tol).cpu().numpy()
+
+
+def _ws_bound(bt, eps):
+    tol = np.zeros(bt.x.size)
+    mask = np.zeros(bt.x.size, bool)
+    for b in range(bt.batch_off.size):
+        off, n, k, wo = (int(bt.batch_off[b]), int(bt.batch_n[b]), int(bt.batch_kmax[b]),
+                         int(bt.w_off[b]))
+        if n <= 0:
+            continue
+        wl = bt.w[wo:wo + k + 1]
+        F = oracle.boys(bt.x[off:off + n], k)
+        tol[off:off + n] = eps * np.abs(wl).sum() + 4 * (k + 1) * U * (np.abs(wl) * F).sum(1)
+        mask[off:off + n] = True
+    return tol, mask
+
+
+def test_weighted_sum_screening_set_every_config():
+    """tol = 1e-10: every argument within 1e-10 sum_l |w_l| plus the
+    accumulation's rounding, and every configuration bitwise equal."""
+    bt = _batches(seed=90)
+    ref = oracle.weighted_sum(bt.x, bt.batch_off, bt.batch_n, bt.batch_kmax, bt.w, bt.w_off)
+    tol, mask = _ws_bound(bt, TOL)
+    saved = boys.weighted_sum_get_config()
+    try:
+        first = None
+        for cfg in range(boys.weighted_sum_num_configs()):
+            boys.weighted_sum_set_config(cfg)
+            got = _ws(bt, tol=1e-10)
+            err = np.abs(got - ref)
+            assert np.all(err[mask] <= tol[mask]), (cfg, float(np.max(err[mask] - tol[mask])))
+            if first is None:
+                first = got
+            else:
+                assert np.array_equal(got[mask], first[mask]), cfg
+    finally:
+        boys.weighted_sum_set_config(saved)
+    paper = _ws(bt)
+    assert not np.array_equal(paper[mask], first[mask])  # a different table set ran
+
+
+@pytest.mark.parametrize("tol", [5e-14, 1e-12, 9.9e-11])
+def test_weighted_sum_paper_tolerances_give_boys_weighted_sum(tol):
+    bt = _batches(seed=91)
+    _, mask = _ws_bound(bt, EPS)
+    assert np.array_equal(_ws(bt, tol=tol)[mask], _ws(bt)[mask])
+
+
+def test_weighted_sum_invalid_tolerance_raises():
+    bt = _batches(seed=92, nbatch=8)
+    for tol in (1e-15, float("nan")):
+        with pytest.raises(boys.BoysError):
+            _ws(bt, tol=tol)
