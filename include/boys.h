@@ -27,12 +27,17 @@
  *  - Domain: x must be >= 0.  Negative x and NaN give NaN in every output
  *    they feed; x = +inf gives 0.
  *  - Accuracy: FP64 results are within 5e-14 absolute of the exact function
- *    for 0 <= k <= 32 (the paper's appendix tables, eps_tol = 5e-14).
- *  - The library keeps a small lazily created workspace per device (for the
- *    batched entry point); boys_finalize() releases it.
+ *    for 0 <= k <= 32 (the paper's appendix tables, eps_tol = 5e-14) and,
+ *    where an entry point accepts them, for orders 33..40 (a table set built
+ *    the same way); the _tol entry points trade this for 1e-10 at lower
+ *    cost; FP32 results are within 1e-6.
+ *  - The library keeps lazily created workspaces per device (the batched
+ *    entry points' prefix arrays and cached graphs, the pair sums' sort
+ *    buffers); boys_finalize() releases them.
  *  - Calls are thread-safe with respect to each other except that two
- *    concurrent boys_weighted_sum calls on one device share its workspace
- *    and must be ordered by the caller (same stream, or synchronised).
+ *    concurrent batched calls (boys_weighted_sum, boys_weighted_sum_tol), or
+ *    two concurrent pair-sum calls, on one device share a workspace and must
+ *    be ordered by the caller (same stream, or synchronised).
  */
 #ifndef BOYS_H
 #define BOYS_H
