@@ -28,9 +28,10 @@
  *    they feed; x = +inf gives 0.
  *  - Accuracy: FP64 results are within 5e-14 absolute of the exact function
  *    for 0 <= k <= 32 (the paper's appendix tables, eps_tol = 5e-14) and,
- *    where an entry point accepts them, for orders 33..40 (a table set built
- *    the same way); the _tol entry points trade this for 1e-10 at lower
- *    cost; FP32 results are within 1e-6.
+ *    where an entry point accepts them (boys_eval_f64(_tol), boys_backward,
+ *    boys_pairsum(_tol)), for orders 33..40 (a table set built the same
+ *    way); the _tol entry points trade this for 1e-10 at lower cost; FP32
+ *    results are within 1e-6.
  *  - The library keeps lazily created workspaces per device (the batched
  *    entry points' prefix arrays and cached graphs, the pair sums' sort
  *    buffers); boys_finalize() releases them.
@@ -215,7 +216,8 @@ BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int
  *
  *   x, y, z  device arrays [n] (FP64); z must not overlap x or y.
  *   c        HOST array of kmax+1 FP64 weights, read during the call.
- *   n        0 <= n <= 2^31 - 1.   kmax 0..32 (the FP64 tables).
+ *   n        0 <= n <= 2^31 - 1.   kmax 0..40 (orders above 32 take the
+ *            high-order tables, as boys_eval_f64).
  * Each z[i] is summed over j in chunks of 512 terms (chunk sums added in
  * order), so its rounding is about (512 + n/512) ulps of sum_j |y_j w_ij|
  * on top of the method's 5e-14 sum_l |c_l| per term.  The arguments are
@@ -231,7 +233,8 @@ BOYS_API int boys_pairsum(const double *x, const double *y, int64_t n, const dou
 /*
  * boys_pairsum with the table set chosen by tol as in boys_eval_f64_tol
  * (tol >= 1e-10: screening set, per-term bound 1e-10 sum_l |c_l|; tol >=
- * 5e-14: the paper's).  Errors: as boys_pairsum, and BOYS_EINVAL for
+ * 5e-14: the paper's; orders above 32 take the high-order tables for any
+ * tol >= 5e-14).  Errors: as boys_pairsum, and BOYS_EINVAL for
  * tol < 5e-14 or NaN.
  */
 BOYS_API int boys_pairsum_tol(const double *x, const double *y, int64_t n, const double *c,

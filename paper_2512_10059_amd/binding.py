@@ -245,8 +245,8 @@ def boys_pairsum(x: torch.Tensor, y: torch.Tensor, c, out: torch.Tensor | None =
         raise BoysError("x and y must have the same length and device")
     ch = np.ascontiguousarray(np.asarray(c.cpu() if isinstance(c, torch.Tensor) else c, dtype=np.float64))
     kmax = ch.size - 1
-    if not 0 <= kmax <= F64_KMAX:
-        raise BoysError(f"c must hold 1..{F64_KMAX + 1} weights")
+    if not 0 <= kmax <= F64_KMAX_EVAL:
+        raise BoysError(f"c must hold 1..{F64_KMAX_EVAL + 1} weights")
     if out is None:
         out = torch.empty_like(x)
     _vector(out, torch.float64, "out")

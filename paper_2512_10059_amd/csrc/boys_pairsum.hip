@@ -33,8 +33,9 @@ namespace {
 
 constexpr int kPairChunk = 512;
 
+// Weights up to the highest order of any table set (40).
 struct PairWeights {
-  double c[kF64Kmax + 1];
+  double c[kHighKmax + 1];
 };
 
 // Region B in closed form.  With g = 1/(2x) the upward recurrence
@@ -49,8 +50,8 @@ struct PairWeights {
 // |c_l| F_0: the absolute rounding stays on the scale of the recurrence's,
 // and an error in F_0 propagates as A_l, exactly as through the recurrence.
 struct PairBPoly {
-  double p[kF64Kmax + 1];  // coefficients of P, degree 0 upwards
-  double q[kF64Kmax + 1];  // coefficients of Q (q[0] = 0)
+  double p[kHighKmax + 1];  // coefficients of P, degree 0 upwards
+  double q[kHighKmax + 1];  // coefficients of Q (q[0] = 0)
 };
 
 // 1/x for finite x in the normal range: the hardware reciprocal refined by
@@ -174,6 +175,12 @@ constexpr auto make_table(std::index_sequence<K...>) {
 }
 constexpr auto kPairTable = make_table<PaperTables>(std::make_index_sequence<kF64Kmax + 1>{});
 constexpr auto kPairTableScreen = make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
+// Orders 33..40: the high-order set.
+template <std::size_t... I>
+constexpr auto make_high_table(std::index_sequence<I...>) {
+  return std::array<PairKernel, sizeof...(I)>{{&pairsum_kernel<kF64Kmax + 1 + int(I), HighTables>...}};
+}
+constexpr auto kPairTableHigh = make_high_table(std::make_index_sequence<kHighKmax - kF64Kmax>{});
 
 // Per-device workspace: sorted keys, indices, permuted y and z, sort scratch.
 struct PairState {
@@ -214,7 +221,7 @@ extern "C" int boys_pairsum(const double *x, const double *y, int64_t n, const d
 extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, const double *c,
                                 int kmax, double tol, double *z, hipStream_t stream) {
   using namespace boys;
-  if (n < 0 || n > (int64_t(1) << 31) - 1 || kmax < 0 || kmax > kF64Kmax) return BOYS_EINVAL;
+  if (n < 0 || n > (int64_t(1) << 31) - 1 || kmax < 0 || kmax > kHighKmax) return BOYS_EINVAL;
   const int set = table_set_for(kmax, tol);
   if (set < 0) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
@@ -226,15 +233,17 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
 
   PairWeights cw{}, dw{};  // c_l, and c_l a_l for region C
+  long double a_hi = kAsymCoefHost[kAsymOrders - 1];  // a_l beyond the table: a_l = a_{l-1} (l - 1/2)
   for (int l = 0; l <= kmax; ++l) {
     cw.c[l] = c[l];
-    dw.c[l] = c[l] * kAsymCoefHost[l];
+    if (l >= kAsymOrders) a_hi *= l - 0.5L;
+    dw.c[l] = c[l] * (l < kAsymOrders ? kAsymCoefHost[l] : double(a_hi));
   }
   // Region B's polynomials P and Q (see PairBPoly), in long double:
   // A_l = a_l g^l with a_l = (2l-1)!!, B_l = sum_j b_j g^j.
   PairBPoly bp{};
   {
-    long double a = 1.0L, b[kF64Kmax + 2] = {}, pq_p[kF64Kmax + 1] = {}, pq_q[kF64Kmax + 1] = {};
+    long double a = 1.0L, b[kHighKmax + 2] = {}, pq_p[kHighKmax + 1] = {}, pq_q[kHighKmax + 1] = {};
     for (int l = 0; l <= kmax; ++l) {
       pq_p[l] = (long double)c[l] * a;
       for (int j = 1; j <= l; ++j) pq_q[j] += (long double)c[l] * b[j];
@@ -294,8 +303,10 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(set == kSetScreen ? kPairTableScreen[kmax] : kPairTable[kmax], dim3(g), dim3(kBlock),
-                     0, stream, keys, ys, n, cw, dw, bp, zs);
+  const PairKernel kernel = set == kSetHigh     ? kPairTableHigh[kmax - kF64Kmax - 1]
+                           : set == kSetScreen ? kPairTableScreen[kmax]
+                                               : kPairTable[kmax];
+  hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
   return hip_status(hipGetLastError());

@@ -42,8 +42,10 @@ def test_paper_distribution_all_rows():
     check(x, y, c, z, np.arange(x.size))
 
 
-@pytest.mark.parametrize("kmax", [0, 1, 5, 20, 32])
+@pytest.mark.parametrize("kmax", [0, 1, 5, 20, 32, 33, 36, 40])
 def test_orders(kmax):
+    """Orders up to 32 with the paper's tables, 33..40 with the high-order
+    set; pair arguments up to 80 cross both sets' region boundaries."""
     x, y, c = workloads.pair_workload(n=600, kmax=kmax, seed=10 + kmax, x_max=40.0)
     check(x, y, c, run(x, y, c), np.arange(0, 600, 3))
 
@@ -76,7 +78,15 @@ def test_invalid_arguments_raise():
     with pytest.raises(boys.BoysError):
         boys.boys_pairsum(x, x[:4].contiguous(), [1.0])
     with pytest.raises(boys.BoysError):
-        boys.boys_pairsum(x, x, np.ones(34))
+        boys.boys_pairsum(x, x, np.ones(42))  # kmax 41
+
+
+def test_high_orders_take_the_high_set_for_any_tolerance():
+    x, y, c = workloads.pair_workload(n=700, kmax=38, seed=77, x_max=40.0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+    a = boys.boys_pairsum(t(x), t(y), c).cpu().numpy()
+    b = boys.boys_pairsum(t(x), t(y), c, tol=1e-10).cpu().numpy()
+    assert np.array_equal(a, b)
 
 
 def test_paper_size_sampled_rows():
