@@ -28,8 +28,8 @@
  *    they feed; x = +inf gives 0.
  *  - Accuracy: FP64 results are within 5e-14 absolute of the exact function
  *    for 0 <= k <= 32 (the paper's appendix tables, eps_tol = 5e-14) and,
- *    where an entry point accepts them (boys_eval_f64(_tol), boys_backward,
- *    boys_pairsum(_tol)), for orders 33..40 (a table set built the same
+ *    where an entry point accepts them (boys_eval_f64(_tol),
+ *    boys_backward(_tol), boys_pairsum(_tol)), for orders 33..40 (a table set built the same
  *    way); the _tol entry points trade this for 1e-10 at lower cost; FP32
  *    results are within 1e-6.
  *  - The library keeps lazily created workspaces per device (the batched
@@ -207,6 +207,18 @@ BOYS_API int boys_weighted_sum_set_config(int config);
  */
 BOYS_API int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax, int64_t ld_g,
                   double *grad_x, hipStream_t stream);
+
+/*
+ * boys_backward with the table set of the recomputation (order kmax+1)
+ * chosen by tol as in boys_eval_f64_tol: tol >= 1e-10 takes the screening
+ * set for kmax <= 31 (each F_{k+1} within 1e-10, so |error| <= 1e-10
+ * sum_k |grad_f[i, k]| plus rounding); 5e-14 <= tol < 1e-10 gives
+ * boys_backward's result bit for bit; kmax 32..39 take the high-order set
+ * for any tol >= 5e-14.  Errors: as boys_backward, and BOYS_EINVAL for
+ * tol < 5e-14 or NaN.
+ */
+BOYS_API int boys_backward_tol(const double *x, const double *grad_f, int64_t n, int kmax,
+                               int64_t ld_g, double tol, double *grad_x, hipStream_t stream);
 
 /*
  * The paper's benchmark workload (Sec. III, Algorithm 2), n^2 Boys

@@ -34,6 +34,7 @@ _SIGNATURES = {
     "boys_eval_f32": ([_P, _I64, _INT, _P, _I64, _P], _INT),
     "boys_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P], _INT),
     "boys_weighted_sum_tol": ([_P, _P, _P, _P, _P, _P, _I32, ctypes.c_double, _P, _P], _INT),
+    "boys_backward_tol": ([_P, _P, _I64, _INT, _I64, ctypes.c_double, _P, _P], _INT),
     "boys_tune_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P,
                                 ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_float)], _INT),
     "boys_weighted_sum_num_configs": ([], _INT),
@@ -214,8 +215,10 @@ def weighted_sum_set_config(config: int):
 
 
 def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None,
-                  out: torch.Tensor | None = None) -> torch.Tensor:
-    """grad_x[i] = -sum_k grad_f[i,k] F_{k+1}(x[i]) for k = 0..kmax."""
+                  out: torch.Tensor | None = None, tol: float | None = None) -> torch.Tensor:
+    """grad_x[i] = -sum_k grad_f[i,k] F_{k+1}(x[i]) for k = 0..kmax.
+
+    tol: None for the paper's tables, else as boys_backward_tol."""
     _vector(x, torch.float64, "x")
     n = x.numel()
     if kmax is None:
@@ -227,8 +230,12 @@ def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None
         out = torch.empty_like(x)
     _vector(out, torch.float64, "grad_x")
     with torch.cuda.device(x.device):
-        _check(lib().boys_backward(_ptr(x), _ptr(grad_f), n, kmax, ld, _ptr(out),
-                                   _stream(x.device)), "boys_backward")
+        if tol is None:
+            _check(lib().boys_backward(_ptr(x), _ptr(grad_f), n, kmax, ld, _ptr(out),
+                                       _stream(x.device)), "boys_backward")
+        else:
+            _check(lib().boys_backward_tol(_ptr(x), _ptr(grad_f), n, kmax, ld, float(tol),
+                                           _ptr(out), _stream(x.device)), "boys_backward_tol")
     return out
 
 
@@ -267,15 +274,18 @@ class BoysFunction(torch.autograd.Function):
     ``BoysFunction.apply(x, kmax)`` returns the (n, kmax+1) FP64 tensor of
     boys_eval_f64; its gradient with respect to x uses dF_k/dx = -F_{k+1},
     which the backward kernel recomputes at order kmax+1.
+    ``BoysFunction.apply(x, kmax, tol)`` does the same at a chosen accuracy
+    (boys_eval_f64_tol forward, boys_backward_tol backward).
     """
 
     @staticmethod
-    def forward(ctx, x, kmax: int):
+    def forward(ctx, x, kmax: int, tol: float | None = None):
         if kmax > F64_KMAX_BACKWARD:
             raise BoysError(f"differentiable evaluation needs kmax <= {F64_KMAX_BACKWARD}")
         ctx.save_for_backward(x)
         ctx.kmax = kmax
-        return boys_eval_f64(x, kmax)
+        ctx.tol = tol
+        return boys_eval_f64(x, kmax) if tol is None else boys_eval_f64_tol(x, kmax, tol)
 
     @staticmethod
     def backward(ctx, grad_f):
@@ -283,8 +293,8 @@ class BoysFunction(torch.autograd.Function):
         grad_x = None
         if ctx.needs_input_grad[0]:
             g = grad_f if grad_f.stride(1) == 1 else grad_f.contiguous()
-            grad_x = boys_backward(x, g, ctx.kmax)
-        return grad_x, None
+            grad_x = boys_backward(x, g, ctx.kmax, tol=ctx.tol)
+        return grad_x, None, None
 
 
 def finalize():

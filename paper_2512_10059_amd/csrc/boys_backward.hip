@@ -199,14 +199,29 @@ constexpr auto make_table(std::index_sequence<K...>) {
       {&backward_kernel<int(K), BackwardSet<int(K)>>...}};
 }
 constexpr auto kBackwardTable = make_table(std::make_index_sequence<kBackwardKmax + 1>{});
+// The screening set recomputes orders up to 32 (kmax up to 31).
+template <std::size_t... K>
+constexpr auto make_screen_table(std::index_sequence<K...>) {
+  return std::array<BackwardKernel, sizeof...(K)>{{&backward_kernel<int(K), ScreenTables>...}};
+}
+constexpr auto kBackwardTableScreen = make_screen_table(std::make_index_sequence<kF64Kmax>{});
 
 }  // namespace
 }  // namespace boys
 
 extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, int kmax,
                              int64_t ld_g, double *grad_x, hipStream_t stream) {
+  return boys_backward_tol(x, grad_f, n, kmax, ld_g, boys::PaperTables::eps, grad_x, stream);
+}
+
+extern "C" int boys_backward_tol(const double *x, const double *grad_f, int64_t n, int kmax,
+                                 int64_t ld_g, double tol, double *grad_x, hipStream_t stream) {
   using namespace boys;
   if (n < 0 || kmax < 0 || kmax > kBackwardKmax || ld_g < kmax + 1) return BOYS_EINVAL;
+  // The set of the recomputation order kmax+1 (orders above 32: the
+  // high-order set for any valid tol).
+  const int set = table_set_for(kmax + 1, tol);
+  if (set < 0) return BOYS_EINVAL;
   if (n == 0) return BOYS_OK;
   if (!x || !grad_f || !grad_x) return BOYS_EINVAL;
   if (n - 1 > (INT64_MAX / 8 - (kmax + 1)) / ld_g) return BOYS_EINVAL;
@@ -219,7 +234,8 @@ extern "C" int boys_backward(const double *x, const double *grad_f, int64_t n, i
   int64_t blocks = (n + block - 1) / block;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
   const int packed = ld_g == kmax + 1 && (reinterpret_cast<uintptr_t>(grad_f) & 15) == 0;
-  hipLaunchKernelGGL(kBackwardTable[kmax], dim3(unsigned(blocks)), dim3(block), 0, stream, x,
-                     grad_f, n, ld_g, grad_x, packed);
+  const BackwardKernel kernel = set == kSetScreen ? kBackwardTableScreen[kmax] : kBackwardTable[kmax];
+  hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(block), 0, stream, x, grad_f, n, ld_g,
+                     grad_x, packed);
   return hip_status(hipGetLastError());
 }

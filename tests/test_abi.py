@@ -105,3 +105,8 @@ def test_tolerance_argument_errors_without_gpu(lib):
     for tol in (1e-15, float("nan")):
         assert w(*([dummy] * 6), 3, tol, dummy, None) == EINVAL
     assert w(*([None] * 6), 0, 1e-10, None, None) == 0
+    b = lib.boys_backward_tol
+    b.argtypes = [P, P, I64, I, I64, D, P, P]
+    for tol in (1e-15, float("nan")):
+        assert b(dummy, dummy, 10, 5, 6, tol, dummy, None) == EINVAL
+    assert b(dummy, dummy, 0, 5, 6, 1e-10, dummy, None) == 0

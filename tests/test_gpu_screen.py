@@ -187,3 +187,39 @@ def test_weighted_sum_invalid_tolerance_raises():
     for tol in (1e-15, float("nan")):
         with pytest.raises(boys.BoysError):
             _ws(bt, tol=tol)
+
+
+# --- the backward pass (boys_backward_tol, BoysFunction with tol) ------------
+
+def _grad_bound(x, G, eps):
+    kmax = G.shape[1] - 1
+    F = oracle.boys(x, kmax + 1)[:, 1:]
+    return eps * np.abs(G).sum(1) + 4 * (kmax + 2) * U * (np.abs(G) * F).sum(1)
+
+
+@pytest.mark.parametrize("kmax", [0, 8, 16, 31])
+def test_backward_screening_set(kmax):
+    x, G = workloads.backward_workload(n=4000, kmax=kmax, seed=300 + kmax)
+    x[:edge_arguments().size] = edge_arguments()
+    g = boys.boys_backward(dev(x), dev(G), kmax, tol=1e-10).cpu().numpy()
+    err = np.abs(g - oracle.backward(x, G))
+    tol = _grad_bound(x, G, TOL)
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+@pytest.mark.parametrize("kmax,tol", [(16, 5e-14), (16, 9.9e-11), (36, 1e-10), (39, 1.0)])
+def test_backward_tolerances_that_select_the_paper_or_high_set(kmax, tol):
+    x, G = workloads.backward_workload(n=3000, kmax=kmax, seed=400 + kmax)
+    a = boys.boys_backward(dev(x), dev(G), kmax).cpu().numpy()
+    b = boys.boys_backward(dev(x), dev(G), kmax, tol=tol).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_autograd_with_screening_tolerance():
+    x, G = workloads.backward_workload(n=3000, kmax=12, seed=500)
+    xt = dev(x).requires_grad_(True)
+    F = boys.BoysFunction.apply(xt, 12, 1e-10)
+    F.backward(dev(G))
+    assert np.abs(F.detach().cpu().numpy() - oracle.boys(x, 12)).max() <= TOL
+    err = np.abs(xt.grad.cpu().numpy() - oracle.backward(x, G))
+    assert np.all(err <= _grad_bound(x, G, TOL))
