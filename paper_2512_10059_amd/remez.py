@@ -294,8 +294,14 @@ def remez(f, rho, a: float, b: float, n: int, m: int, tol: float = 1e-6, max_ite
 
     f and rho are vectorised long-double functions.  Returns the pole-free
     equioscillating r = p/q with monic q.  ``target``: abort early (step 6)
-    when the levelled error cannot reach it.  Raises RemezFailure."""
-    mp.mp.dps = dps
+    when the levelled error cannot reach it.  Raises RemezFailure.  mpmath
+    runs at ``dps`` digits inside the call; the caller's precision is left
+    as it was."""
+    with mp.workdps(dps):
+        return _remez(f, rho, a, b, n, m, tol, max_iter, grid_size, seed, target, verbose)
+
+
+def _remez(f, rho, a, b, n, m, tol, max_iter, grid_size, seed, target, verbose) -> RemezResult:
     N = n + m + 2
     rng = np.random.default_rng(seed)
     y = _fine_grid(a, b, grid_size)
@@ -401,7 +407,7 @@ def region_x0(kmax: int) -> float:
 def region_x1(kmax: int, eps: float, guess: float = 20.0) -> float:
     """x1 solving Gamma(kmax+1/2, x1) / (2 x1^(kmax+1/2)) = eps (the asymptote's
     error for F_kmax), by Newton's method in mpmath."""
-    mp.mp.dps = 40
-    s = kmax + mp.mpf(1) / 2
-    g = lambda x: mp.gammainc(s, x) / (2 * x ** s) - eps
-    return float(mp.findroot(g, guess))
+    with mp.workdps(40):
+        s = kmax + mp.mpf(1) / 2
+        g = lambda x: mp.gammainc(s, x) / (2 * x ** s) - eps
+        return float(mp.findroot(g, guess))

@@ -21,6 +21,8 @@ requires each break to be caught.
 """
 from __future__ import annotations
 
+import functools
+
 import mpmath as mp
 import numpy as np
 
@@ -180,6 +182,17 @@ def check_branch_continuity(o):
     assert float(rel.max()) <= 1e-17, f"branch jump at 30: {float(rel.max())}"
 
 
-ALL_CHECKS = [check_value_at_zero, check_erf_closed_form, check_gammainc, check_quadrature,
-              check_recurrences, check_asymptote, check_monotone_and_bounds, check_derivative,
-              check_branch_continuity]
+def _at_40_digits(check):
+    """Runs a check with mpmath at 40 digits, whatever precision other code in
+    the process left set."""
+    @functools.wraps(check)
+    def run(o, *args, **kwargs):
+        with mp.workdps(40):
+            return check(o, *args, **kwargs)
+    return run
+
+
+ALL_CHECKS = [_at_40_digits(c) for c in (
+    check_value_at_zero, check_erf_closed_form, check_gammainc, check_quadrature,
+    check_recurrences, check_asymptote, check_monotone_and_bounds, check_derivative,
+    check_branch_continuity)]
