@@ -27,46 +27,48 @@ __device__ __forceinline__ double fma_uniform_addend(double a, double b, double 
   return r;
 }
 
-// ---------------------------------------------------------------------------
-// e^{-x} for the VALU-bound kernels, table-driven (Tang's method for the
-// exponential, ACM TOMS 15(2), 1989).  With N = -rint(128 x / ln2) and
-// r = x + N ln2/128 (|r| <= ln2/256 plus rounding, ln2/128 carried as a
-// two-double sum L_hi + L_lo),
-//     e^{-x} = 2^(N >> 7) * 2^((N & 127)/128) * e^{-r},
-// the middle factor from a 128-entry table of correctly rounded 2^(i/128)
-// held in LDS by the calling kernel, and e^{-r} - 1 from its degree-5 Taylor
-// polynomial -(r/120)(r^4 - 5r^3 + 20r^2 - 60r + 120), whose truncation is
-// below 1e-18 relative here.  The result is within about 2^-52 relative
-// (table rounding plus one final rounding), against about 46 VALU
-// instructions of the library routine this takes 16, since the domain needs
-// no overflow, underflow or special-value handling: the callers pass
-// 0 <= x < 2^10 or NaN (NaN propagates through r).
-constexpr int kExpTableLen = 1 << BOYS_EXP_TABLE_BITS;
-static __constant__ const double kExp2Table[kExpTableLen] = BOYS_EXP_TABLE_INIT;
-
-// Copies the table to LDS; the caller synchronises the block before use.
-__device__ __forceinline__ void load_exp_table(double *s_tab) {
-  for (int t = threadIdx.x; t < kExpTableLen; t += blockDim.x) s_tab[t] = kExp2Table[t];
+// a + c for a compile-time (hence wave-uniform) c, issued as VOP3 v_add_f64
+// with c in an SGPR pair; written as asm so that it is not contracted with
+// the product that feeds it.
+__device__ __forceinline__ double add_uniform(double a, double c) {
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(c));
+  return r;
 }
 
-// e^{-x} (see above).  The constants are literals; the Horner steps take
-// theirs as SGPR addends.
-constexpr double kExpInvL = BOYS_EXP_INV_L;
-constexpr double kExpLHi = BOYS_EXP_L_HI;
-constexpr double kExpLLo = BOYS_EXP_L_LO;
+// ---------------------------------------------------------------------------
+// e^{-x} for the VALU-bound kernels, without a table: Cody and Waite's
+// argument reduction, then a Taylor polynomial.  With n = rint(x/ln2) and
+// r = n ln2 - x (ln2 carried as LN2_HI + LN2_LO, |r| <= ln2/2 plus rounding),
+//     e^{-x} = 2^(-n) * e^r,
+// and e^r from its degree-13 Taylor polynomial, whose truncation is below
+// 1e-17 relative.  n LN2_HI - x is exact under the fused multiply-add (both
+// terms are multiples of 2^-53 within 1/2 of each other when x >= 1/2, and
+// n = 0 below), so the reduction rounds once, in the LN2_LO step.  The result
+// is within about 2^-52 relative.  Against about 46 VALU instructions of the
+// library routine this takes 21, since the domain needs no overflow,
+// underflow or special-value handling: the callers pass 0 <= x < 2^10 or NaN
+// (NaN propagates through r; past x = 708 the scaling underflows to 0, on
+// lanes whose result is discarded).
+constexpr double kExpInvLn2 = BOYS_EXP_INV_LN2;
+constexpr double kExpLn2Hi = BOYS_EXP_LN2_HI;
+constexpr double kExpLn2Lo = BOYS_EXP_LN2_LO;
+constexpr int kExpDegree = BOYS_EXP_DEGREE;
+constexpr double kExpTaylor[kExpDegree + 1] = BOYS_EXP_TAYLOR_INIT;
 
-__device__ __forceinline__ double exp_neg(double x, const double *s_tab) {
-  const double nd = __builtin_rint(x * kExpInvL);
-  double r = __builtin_fma(-nd, kExpLHi, x);
-  r = __builtin_fma(-nd, kExpLLo, r);
-  const int N = -int(nd);
-  const double T = s_tab[N & (kExpTableLen - 1)];
-  double v = r - 5.0;
-  v = fma_uniform_addend(v, r, 20.0);
-  v = fma_uniform_addend(v, r, -60.0);
-  v = fma_uniform_addend(v, r, 120.0);
-  const double q = (r * (-1.0 / 120.0)) * v;  // e^{-r} - 1
-  return __builtin_amdgcn_ldexp(__builtin_fma(T, q, T), N >> BOYS_EXP_TABLE_BITS);
+// e^{-x} (see above).  The constants are literals; the Horner steps take
+// theirs as SGPR addends.  The top term is a product and a sum, each with
+// one SGPR operand, instead of a fused multiply-add with two constants, one
+// of which would first be moved into VGPRs; its extra rounding is on a term
+// below 2^-52 of the result.
+__device__ __forceinline__ double exp_neg(double x) {
+  const double nd = __builtin_rint(x * kExpInvLn2);
+  double r = __builtin_fma(nd, kExpLn2Hi, -x);
+  r = __builtin_fma(nd, kExpLn2Lo, r);
+  double p = add_uniform(r * kExpTaylor[kExpDegree], kExpTaylor[kExpDegree - 1]);
+#pragma unroll
+  for (int j = kExpDegree - 2; j >= 0; --j) p = fma_uniform_addend(p, r, kExpTaylor[j]);
+  return __builtin_amdgcn_ldexp(p, -int(nd));
 }
 
 // ---------------------------------------------------------------------------
@@ -221,9 +223,8 @@ constexpr int kTableLen = kF64Kmax + 1 + 2 * kPad;
 
 // Region A: r_{A,k}, then F_l = (2x F_{l+1} + e^-x) * (1/(2l+1)) downwards.
 template <class T = PaperTables>
-__device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down,
-                                                const double *s_exp) {
-  const double e = exp_neg(x, s_exp);
+__device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down) {
+  const double e = exp_neg(x);
   const double two_x = x + x;
   double F = rational_a_rt<T>(x, k);
   double acc = wk * F;
@@ -242,9 +243,8 @@ __device__ __forceinline__ double wsum_region_a(double x, int k, double wk, cons
 
 // Region B: r_B, then F_{l+1} = ((2l+1) F_l - e^-x) / (2x) upwards.
 template <class T = PaperTables>
-__device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up,
-                                                const double *s_exp) {
-  const double e = exp_neg(x, s_exp);
+__device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up) {
+  const double e = exp_neg(x);
   const double inv_2x = 0.5 / x;
   double F = rational_b_t<T>(x);
   double acc = w0 * F;

@@ -68,11 +68,10 @@ __device__ __forceinline__ double recip(double x) {
 // with the table set T.
 template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
-                                                const PairWeights &dw, const wpair *pq,
-                                                const double *s_exp) {
+                                                const PairWeights &dw, const wpair *pq) {
   double acc;
   if (x < T::x0) {
-    const double e = exp_neg(x, s_exp);
+    const double e = exp_neg(x);
     const double two_x = x + x;
     double F = rational_a_t<K, T>(x);
     acc = cw.c[K] * F;
@@ -91,7 +90,7 @@ __device__ __forceinline__ double pair_weighted(double x, const PairWeights &cw,
     for (int l = K - 1; l >= 0; --l) P = fma_uniform_addend(P, g, dw.c[l]);
     acc = P * r;
   } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l)
-    const double e = exp_neg(x, s_exp);
+    const double e = exp_neg(x);
     const double g = 0.5 * recip(x);
     const double F0 = rational_b_t<T>(x);
     // Chunks of four steps (one chunk rolled), so at most four coefficient
@@ -125,9 +124,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
                                                          PairWeights cw, PairWeights dw, PairBPoly bp,
                                                          double *__restrict__ zs) {
   __shared__ double s_x[kPairChunk], s_y[kPairChunk];
-  __shared__ double s_exp[kExpTableLen];
   __shared__ wpair s_pq[K + 1];
-  load_exp_table(s_exp);  // made visible by the first barrier below
   if (threadIdx.x <= K) s_pq[threadIdx.x] = wpair{bp.p[threadIdx.x], bp.q[threadIdx.x]};
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
@@ -142,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
     double part = 0.0;
     for (int t = 0; t < m; ++t)
-      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + s_x[t]), cw, dw, s_pq, s_exp), part);
+      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + s_x[t]), cw, dw, s_pq), part);
     total += part;
     __syncthreads();
   }

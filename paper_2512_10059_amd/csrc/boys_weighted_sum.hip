@@ -245,7 +245,6 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   __shared__ wpair s_down[kWavesPerBlock][kTableLen];  // (w_l, 1/(2l+1))
   __shared__ wpair s_up[kWavesPerBlock][kTableLen];    // (w_{l+1}, 2l+1)
   __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];  // sorted arguments, then their results
-  __shared__ double s_exp[kExpTableLen];
   __shared__ __attribute__((aligned(16))) double s_asym[kWavesPerBlock][kAsymTableLen];  // w_l a_l
 
   const int tid = threadIdx.x;
@@ -260,7 +259,6 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
     s_down[wv][t] = wpair{0.0, 1.0 / double(2 * l + 1)};
     s_up[wv][t] = wpair{0.0, double(2 * l + 1)};
   }
-  load_exp_table(s_exp);
   __syncthreads();  // the only block-wide barrier: waves work independently below
   wpair *const down = &s_down[wv][kPad];
   wpair *const up = &s_up[wv][kPad];
@@ -348,9 +346,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (q < count) {
           const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a<TS>(xq, k, wk, down, s_exp);
+          if (q < nA) acc = wsum_region_a<TS>(xq, k, wk, down);
           else if (q < nAC) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b<TS>(xq, k, w0, up, s_exp);
+          else acc = wsum_region_b<TS>(xq, k, w0, up);
           s_x[wv][q] = acc;
         }
       }
@@ -369,9 +367,9 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < TS::x0) acc = wsum_region_a<TS>(xq, k, wk, down, s_exp);
+          if (xq < TS::x0) acc = wsum_region_a<TS>(xq, k, wk, down);
           else if (region_c<TS>(xq)) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b<TS>(xq, k, w0, up, s_exp);
+          else acc = wsum_region_b<TS>(xq, k, w0, up);
           a.out[first + p] = acc;
         }
       }
@@ -390,26 +388,28 @@ struct WsConfig {
   WsKernel kernel_screen;  // the screening tables (eps_tol = 1e-10)
   int items;               // arguments per lane per tile (tile = 64 * items)
   int bin;                 // region binning in LDS
-  int blocks_per_cu;
+  int rounds;              // grid = rounds x the workgroups resident per CU x CUs
   const char *name;
 };
 
-#define BOYS_WS_CONFIG(ITEMS, BIN, WG, NAME) \
-  {&ws_kernel<ITEMS, BIN, PaperTables>, &ws_kernel<ITEMS, BIN, ScreenTables>, ITEMS, BIN, WG, NAME}
+// Grids are counted in rounds of resident workgroups: the waves split the
+// cost evenly, so a partial last round leaves CUs idle while it runs.
+#define BOYS_WS_CONFIG(ITEMS, BIN, R, NAME) \
+  {&ws_kernel<ITEMS, BIN, PaperTables>, &ws_kernel<ITEMS, BIN, ScreenTables>, ITEMS, BIN, R, NAME}
 const WsConfig kConfigs[] = {
-    BOYS_WS_CONFIG(4, true, 8, "wave-tile256-bin-8wg"),
-    BOYS_WS_CONFIG(4, true, 12, "wave-tile256-bin-12wg"),
-    BOYS_WS_CONFIG(4, true, 16, "wave-tile256-bin-16wg"),
-    BOYS_WS_CONFIG(8, true, 8, "wave-tile512-bin-8wg"),
-    BOYS_WS_CONFIG(8, true, 12, "wave-tile512-bin-12wg"),
-    BOYS_WS_CONFIG(2, true, 12, "wave-tile128-bin-12wg"),
-    BOYS_WS_CONFIG(4, false, 12, "wave-tile256-nobin-12wg"),
-    BOYS_WS_CONFIG(2, false, 12, "wave-tile128-nobin-12wg"),
-    BOYS_WS_CONFIG(8, true, 16, "wave-tile512-bin-16wg"),
+    BOYS_WS_CONFIG(4, true, 1, "wave-tile256-bin-1round"),
+    BOYS_WS_CONFIG(4, true, 2, "wave-tile256-bin-2rounds"),
+    BOYS_WS_CONFIG(4, true, 3, "wave-tile256-bin-3rounds"),
+    BOYS_WS_CONFIG(8, true, 1, "wave-tile512-bin-1round"),
+    BOYS_WS_CONFIG(8, true, 2, "wave-tile512-bin-2rounds"),
+    BOYS_WS_CONFIG(2, true, 2, "wave-tile128-bin-2rounds"),
+    BOYS_WS_CONFIG(4, false, 2, "wave-tile256-nobin-2rounds"),
+    BOYS_WS_CONFIG(2, false, 2, "wave-tile128-nobin-2rounds"),
+    BOYS_WS_CONFIG(8, true, 3, "wave-tile512-bin-3rounds"),
 };
 #undef BOYS_WS_CONFIG
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
-constexpr int kDefaultConfig = 4;  // wave-tile512-bin-12wg
+constexpr int kDefaultConfig = 8;  // wave-tile512-bin-3rounds
 
 // ---------------------------------------------------------------------------
 // Per-device state: workspace, one cached graph per configuration (so the
@@ -560,8 +560,13 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set) {
   WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
   void *main_args[] = {&args};
   hipKernelNodeParams mp = {};
-  mp.func = reinterpret_cast<void *>(set ? conf.kernel_screen : conf.kernel);
-  mp.gridDim = dim3(unsigned(s.cus * conf.blocks_per_cu));
+  const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
+  int resident = 0;
+  BOYS_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern),
+                                                            kBlock, 0));
+  if (resident < 1) resident = 1;
+  mp.gridDim = dim3(unsigned(s.cus * resident * conf.rounds));
+  mp.func = reinterpret_cast<void *>(kern);
   mp.blockDim = dim3(kBlock);
   mp.sharedMemBytes = 0;
   mp.kernelParams = main_args;

@@ -1,13 +1,15 @@
 """Constants of the VALU-bound consumer kernels (batched weighted sums, pair
-sums): the table-driven e^{-x} and the region-C coefficients.
+sums): the table-free e^{-x} and the region-C coefficients.
 
 Pins, none of which reuses the generator's arithmetic:
-* every table entry T_i is the double nearest 2^(i/128), checked in exact
-  integer arithmetic: 2^i lies between (T_i - ulp/2)^128 and (T_i + ulp/2)^128;
-* ln2/128 = L_HI + L_LO to 1e-32 relative, checked through exp, not log;
+* every Taylor coefficient c_j is the double nearest 1/j!, checked in exact
+  integer arithmetic: |c_j j! - 1| <= j! ulp(c_j)/2;
+* ln2 = LN2_HI + LN2_LO to 1e-32 relative, checked through exp, not log,
+  and 1/ln2 through its product with LN2_HI;
 * the kernel's sequence of roundings (fused multiply-adds emulated exactly
   with rationals) stays within 2^-52 relative of e^{-x} on [0, 32), the
-  bound of the method (table rounding plus one final rounding);
+  bound stated for the routine (one rounding in the reduction, Horner's
+  roundings damped by |r| <= ln2/2, truncation below 1e-17);
 * a_l = Gamma(l + 1/2)/2 is the double nearest (sqrt(pi)/2) prod_{m<l} (m + 1/2),
   the product taken exactly in rationals (the generator uses the gamma
   function), and a_l x^(-l-1/2) reproduces the upward asymptote recurrence."""
@@ -29,9 +31,9 @@ def load():
     text = open(HEADER).read().replace("\\\n", " ")
     d = dict(re.findall(r"^#define\s+(\w+)\s+(.*)$", text, re.M))
     vec = lambda name: [float.fromhex(v.strip()) for v in d[name].strip()[1:-1].split(",")]
-    return dict(bits=int(d["BOYS_EXP_TABLE_BITS"]), inv_l=float.fromhex(d["BOYS_EXP_INV_L"]),
-                l_hi=float.fromhex(d["BOYS_EXP_L_HI"]), l_lo=float.fromhex(d["BOYS_EXP_L_LO"]),
-                tab=vec("BOYS_EXP_TABLE_INIT"), asym=vec("BOYS_ASYM_COEF_INIT"),
+    return dict(inv_ln2=float.fromhex(d["BOYS_EXP_INV_LN2"]), ln2_hi=float.fromhex(d["BOYS_EXP_LN2_HI"]),
+                ln2_lo=float.fromhex(d["BOYS_EXP_LN2_LO"]), degree=int(d["BOYS_EXP_DEGREE"]),
+                taylor=vec("BOYS_EXP_TAYLOR_INIT"), asym=vec("BOYS_ASYM_COEF_INIT"),
                 asym_orders=int(d["BOYS_ASYM_ORDERS"]))
 
 
@@ -47,47 +49,60 @@ def fma(a, b, c):
 def exp_neg_emulated(x):
     """The device routine's operations in its order, each rounded as the
     hardware rounds it."""
-    nd = float(round(x * C["inv_l"]))          # v_rndne_f64 of the rounded product
-    r = fma(-nd, C["l_hi"], x)
-    r = fma(-nd, C["l_lo"], r)
-    N = -int(nd)
-    T = C["tab"][N & ((1 << C["bits"]) - 1)]
-    v = r - 5.0
-    v = fma(v, r, 20.0)
-    v = fma(v, r, -60.0)
-    v = fma(v, r, 120.0)
-    q = (r * (-1.0 / 120.0)) * v
-    return math.ldexp(fma(T, q, T), N >> C["bits"])
+    nd = float(round(x * C["inv_ln2"]))        # v_rndne_f64 of the rounded product
+    r = fma(nd, C["ln2_hi"], -x)
+    r = fma(nd, C["ln2_lo"], r)
+    c = C["taylor"]
+    p = float(Fraction(r) * Fraction(c[-1]))   # top term: product, then sum
+    p = float(Fraction(p) + Fraction(c[-2]))
+    for j in range(len(c) - 3, -1, -1):
+        p = fma(p, r, c[j])
+    return math.ldexp(p, -int(nd))
 
 
-def test_table_is_correctly_rounded():
-    n = 1 << C["bits"]
-    assert len(C["tab"]) == n
-    for i, t in enumerate(C["tab"]):
-        assert 1.0 <= t < 2.0
-        half_ulp = Fraction(math.ulp(t)) / 2
-        lo, hi = Fraction(t) - half_ulp, Fraction(t) + half_ulp
-        target = Fraction(2) ** i
-        assert lo ** n <= target <= hi ** n, f"entry {i} is not the nearest double to 2^({i}/{n})"
+def test_taylor_coefficients_are_correctly_rounded():
+    assert C["degree"] == 13 and len(C["taylor"]) == C["degree"] + 1
+    for j, cj in enumerate(C["taylor"]):
+        fact = math.factorial(j)
+        assert abs(Fraction(cj) * fact - 1) <= Fraction(math.ulp(cj)) / 2 * fact, f"c_{j} is not the nearest double to 1/{j}!"
 
 
-def test_split_of_ln2_over_table_length():
+def test_taylor_truncation_bound():
+    """The first omitted term at |r| = ln2/2 bounds the truncation: below 1e-17
+    relative (Lagrange remainder e^xi r^14/14!, |xi| <= |r|, over e^r)."""
+    r = math.log(2) / 2 * (1 + 1e-12)
+    d = C["degree"] + 1
+    assert r ** d / math.factorial(d) * math.exp(r) / math.exp(-r) < 1e-17
+
+
+def test_split_of_ln2():
     mp.mp.dps = 50
-    n = 1 << C["bits"]
-    s = mp.mpf(C["l_hi"]) + mp.mpf(C["l_lo"])
-    assert abs(mp.exp(n * s) / 2 - 1) < mp.mpf("1e-32")
-    assert abs(C["l_lo"]) <= math.ulp(C["l_hi"])       # a genuine two-part split
-    assert abs(C["inv_l"] * C["l_hi"] - 1.0) < 1e-15
+    s = mp.mpf(C["ln2_hi"]) + mp.mpf(C["ln2_lo"])
+    assert abs(mp.exp(s) / 2 - 1) < mp.mpf("1e-32")
+    assert abs(C["ln2_lo"]) <= math.ulp(C["ln2_hi"])   # a genuine two-part split
+    assert abs(C["inv_ln2"] * C["ln2_hi"] - 1.0) < 1e-15
+
+
+def test_reduction_first_step_is_exact():
+    """n LN2_HI - x needs no rounding for the n that rint(x/ln2) picks on the
+    kernels' domain (checked exactly in rationals)."""
+    rng = np.random.default_rng(7)
+    for x in list(rng.uniform(0.0, 1024.0, 2000)) + list(rng.uniform(0.0, 1.0, 500)):
+        x = float(x)
+        nd = float(round(x * C["inv_ln2"]))
+        exact = Fraction(nd) * Fraction(C["ln2_hi"]) - Fraction(x)
+        assert Fraction(fma(nd, C["ln2_hi"], -x)) == exact
 
 
 def arguments():
     rng = np.random.default_rng(42)
     pts = list(rng.uniform(0.0, 32.0, 3000)) + list(np.exp(rng.uniform(np.log(1e-300), np.log(1.0), 500)))
-    L = math.log(2) / (1 << C["bits"])
-    for m in (1, 2, 63, 64, 127, 128, 129, 1000, 5000, 5900):   # reduction interval edges
+    L = math.log(2)
+    for m in range(0, 47):                        # reduction interval edges
         c = (m + 0.5) * L
         pts += [np.nextafter(c, 0.0), c, np.nextafter(c, 99.0), m * L]
-    pts += [0.0, 5e-324, 1e-17, 11.899848152108484, 28.98933773882074, 31.999]
+    pts += [0.0, 5e-324, 1e-17, 11.899848152108484, 14.842842360917231, 23.149988540679747,
+            28.98933773882074, 30.455574446774907, 31.999]
     return pts
 
 
@@ -102,19 +117,23 @@ def test_emulated_routine_within_two_ulps_relative():
     assert worst <= 2.0 ** -52, f"worst relative error {worst:.3e}"
 
 
-@pytest.mark.parametrize("mutation", ["index", "sign", "lo", "coef"])
+@pytest.mark.parametrize("mutation", ["order", "sign", "lo", "pick", "degree"])
 def test_emulation_detects_planted_mistakes(mutation):
     """The accuracy check above fails for plausible mistakes in the routine."""
     saved = dict(C)
     try:
-        if mutation == "index":
-            C["tab"] = C["tab"][1:] + C["tab"][:1]
+        if mutation == "order":
+            t = list(C["taylor"])
+            t[3], t[4] = t[4], t[3]
+            C["taylor"] = t
         elif mutation == "sign":
-            C["l_hi"] = -C["l_hi"]
+            C["ln2_hi"] = -C["ln2_hi"]
         elif mutation == "lo":
-            C["l_lo"] = 0.0
-        elif mutation == "coef":
-            C["inv_l"] = C["inv_l"] * 0.5   # picks the wrong N: |r| leaves the polynomial's range
+            C["ln2_lo"] = 0.0
+        elif mutation == "pick":
+            C["inv_ln2"] = C["inv_ln2"] * 0.5   # picks the wrong n: |r| leaves the polynomial's range
+        elif mutation == "degree":
+            C["taylor"] = C["taylor"][:-2]      # degree 11: truncation 6e-15 at |r| = ln2/2
         with pytest.raises(AssertionError):
             test_emulated_routine_within_two_ulps_relative()
     finally:
