@@ -33,6 +33,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "boys.h"
 #include "boys_common.hpp"
@@ -224,6 +225,11 @@ __device__ __forceinline__ int32_t wave_search(const int64_t *cost_start, int32_
   return L;
 }
 
+// Mask of lanes 0..r-1 (r <= 0: none, r >= 64: all).
+__device__ __forceinline__ uint64_t lane_prefix_mask(int r) {
+  return r >= 64 ? ~uint64_t(0) : (r <= 0 ? uint64_t(0) : (uint64_t(1) << r) - 1);
+}
+
 // Orders LDS accesses of one wave (the hardware executes a wave's LDS
 // instructions in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_sync() {
@@ -249,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const uint32_t lane8 = uint32_t(lane) * 8u;  // the lane's byte offset in a 64-double row
   // The wave index is the same in every lane; saying so keeps the per-wave
   // cost range, the batch fields and the order k in scalar registers, so
   // loops over k and the choice of r_A,k branch on scalar conditions.
@@ -296,49 +303,76 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
       load_weights(a.w + f.woff, k, lane, down, up, s_asym[wv], w0, wk);
       reload = false;
     }
+    // Argument loads: one wave-uniform base (the tile's first argument) and
+    // a 32-bit byte offset per lane, so the loads take the scalar-base form
+    // with the item's 512-byte step as immediate offset.  In a partial tile
+    // the offsets are clamped to the last argument, so every load stays in
+    // the tile and all ITEMS loads are in flight together; lanes past the end
+    // are never evaluated or stored.
+    const char *const tx = reinterpret_cast<const char *>(a.x + first);
     double xv[ITEMS];
+    if (count == T) {
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int p = it * 64 + lane;
-      // Unconditional load from an index clamped into the tile (count >= 1),
-      // so the ITEMS loads are in flight together; lanes past the end are
-      // never evaluated or stored.
-      xv[it] = a.x[first + (p < count ? p : count - 1)];
+      for (int it = 0; it < ITEMS; ++it)
+        xv[it] = *reinterpret_cast<const double *>(tx + (lane8 + uint32_t(it) * 512u));
+    } else {
+      const uint32_t last8 = uint32_t(count - 1) * 8u;
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t o = lane8 + uint32_t(it) * 512u;
+        xv[it] = *reinterpret_cast<const double *>(tx + (o < last8 ? o : last8));
+      }
     }
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) xv[it] = domain(xv[it]);
     if constexpr (BIN) {
-      int cls[ITEMS];
-#pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
-        const int p = it * 64 + lane;
-        cls[it] = p >= count ? 3 : (xv[it] < TS::x0 ? 0 : (region_c<TS>(xv[it]) ? 1 : 2));
-      }
       // Classes in the order A, C, B: the two 64-lane passes that straddle a
       // class boundary then pair the cheap asymptote path with one of the
       // rational paths instead of both rational paths.  Class c goes to
-      // [start_c, start_c + count_c): running base per class.
-      // Each lane keeps the sorted slot of each of its items; results are
-      // written back into the slots, then stored in the original order with
-      // coalesced stores (scattered 8-byte stores into the tile had written
-      // 15-50% more bytes to HBM than the output holds).
-      int base = 0, nA = 0, nAC = 0;
-      int slot[ITEMS] = {};  // items past the tile's end keep 0 and are not stored
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      // [start_c, start_c + count_c).  A first sweep counts classes A and C
+      // (ballots of one compare each per item); B is the rest of the valid
+      // lanes.  A second sweep gives each lane its slot: the running base of
+      // its class plus its rank in the class among the item's lanes, where
+      // the ranks in A and C are lane-prefix counts of their masks and the
+      // rank in B is the lane index minus both (valid lanes form a prefix).
+      // Each lane keeps the slots of its items; results are written back
+      // into them, then stored in the original order with coalesced stores.
+      int nA = 0, nC = 0;
+      int slot[ITEMS];
+      auto bin = [&](auto full) {
+        constexpr bool kFull = decltype(full)::value;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-          const uint64_t m = __ballot(cls[it] == c);
-          if (cls[it] == c) {
-            slot[it] = base + int(__builtin_amdgcn_mbcnt_hi(
-                                  uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
-            s_x[wv][slot[it]] = xv[it];
-          }
-          base += __popcll(m);
+          const uint64_t valid = kFull ? ~uint64_t(0) : lane_prefix_mask(count - it * 64);
+          nA += __popcll(__ballot(xv[it] < TS::x0) & valid);
+          nC += __popcll(__ballot(region_c<TS>(xv[it])) & valid);
         }
-        if (c == 0) nA = base;
-        if (c == 1) nAC = base;
-      }
+        int bA = 0, bC = nA, bB = nA + nC;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          // The compares again, rather than 2*ITEMS masks held in scalar
+          // registers across the sweeps.
+          double xr = xv[it];
+          asm volatile("" : "+v"(xr));
+          const uint64_t valid = kFull ? ~uint64_t(0) : lane_prefix_mask(count - it * 64);
+          const bool isA = xr < TS::x0;
+          const bool isC = region_c<TS>(xr);  // x1 > x0: never with isA
+          const uint64_t mA = __ballot(isA) & valid;
+          const uint64_t mC = __ballot(isC) & valid;
+          const int rA = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mA >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mA), 0u)));
+          const int rC = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mC >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mC), 0u)));
+          slot[it] = isA ? bA + rA : (isC ? bC + rC : bB + (lane - rA - rC));
+          if (kFull || it * 64 + lane < count) s_x[wv][slot[it]] = xv[it];
+          const int cA = __popcll(mA), cC = __popcll(mC);
+          const int cV = kFull ? 64 : __popcll(valid);
+          bA += cA;
+          bC += cC;
+          bB += cV - cA - cC;
+        }
+      };
+      if (count == T) bin(std::true_type{});
+      else bin(std::false_type{});
+      const int nAC = nA + nC;
       wave_sync();
 #pragma unroll 1
       for (int it = 0; it < ITEMS; ++it) {
@@ -353,10 +387,17 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
         }
       }
       wave_sync();
+      char *const to = reinterpret_cast<char *>(a.out + first);
+      if (count == T) {
 #pragma unroll
-      for (int it = 0; it < ITEMS; ++it) {
-        const int p = it * 64 + lane;
-        if (p < count) a.out[first + p] = s_x[wv][slot[it]];
+        for (int it = 0; it < ITEMS; ++it)
+          *reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)) = s_x[wv][slot[it]];
+      } else {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          const double v = s_x[wv][slot[it]];
+          if (it * 64 + lane < count) *reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)) = v;
+        }
       }
       wave_sync();
     } else {

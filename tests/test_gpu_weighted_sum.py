@@ -224,3 +224,42 @@ def test_more_batches_than_one_scan_round():
     bt = workloads.Batches(x=x, batch_off=off, batch_n=n, batch_kmax=k, w=w, w_off=w_off)
     out = boys.boys_weighted_sum(*to_dev(bt)).cpu().numpy()
     check(bt, out)
+
+
+@pytest.mark.parametrize("config", range(16))
+def test_partial_tiles_write_only_their_batch(config):
+    """Batches separated by gaps in the argument and output arrays, with sizes
+    around the tile lengths (1..1100: every partial-tile shape of tiles of 128,
+    256 and 512): every argument of every batch matches the oracle, and the
+    gaps keep the sentinel the output was filled with.  The last batch ends at
+    the end of both arrays, so a load or store past a tile would leave them."""
+    if config >= boys.weighted_sum_num_configs():
+        pytest.skip("no such configuration")
+    rng = np.random.default_rng(21)
+    n = np.array([1, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700, 1023, 1024, 1100, 5, 0, 3],
+                 dtype=np.int32)
+    gap = rng.integers(1, 40, n.size)
+    off = np.zeros(n.size, np.int64)
+    pos = 0
+    for b in range(n.size):
+        pos += int(gap[b])
+        off[b] = pos
+        pos += int(n[b])
+    total = pos  # the last batch ends the arrays
+    k = rng.integers(0, 33, n.size).astype(np.int32)
+    w_off = np.concatenate([[0], np.cumsum(k[:-1] + 1)]).astype(np.int64)
+    w = rng.standard_normal(int((k + 1).sum()))
+    x = workloads.gaussian_pair_arguments(total, seed=22)
+    bt = workloads.Batches(x=x, batch_off=off, batch_n=n, batch_kmax=k, w=w, w_off=w_off)
+    sentinel = -12345.0
+    out_dev = torch.full((total,), sentinel, dtype=torch.float64, device=DEV)
+    boys.weighted_sum_set_config(config)
+    try:
+        out = boys.boys_weighted_sum(*to_dev(bt), out=out_dev).cpu().numpy()
+    finally:
+        boys.weighted_sum_set_config(-1)
+    check(bt, out)
+    inside = np.zeros(total, bool)
+    for b in range(n.size):
+        inside[off[b]:off[b] + n[b]] = True
+    assert np.all(out[~inside] == sentinel)
