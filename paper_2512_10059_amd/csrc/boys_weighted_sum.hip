@@ -74,39 +74,61 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
 }
 
 // Exclusive prefix sums of tiles and cost over the batches (one workgroup).
-// The table is taken in rounds of kScanThreads * kScanPer batches; thread t
-// owns kScanPer consecutive batches of a round, loads them all at once (the
-// loop is unrolled, so their latencies overlap) and keeps their counts in
-// registers for the write-back.  Tiles are powers of two (1 << tile_shift
-// arguments), so every count is an add and a shift.  Thread totals are
-// scanned within each wave by lane shuffles and across the waves in LDS.
+// The table is taken in rounds of kScanThreads * kScanPer batches.  Each
+// round goes through LDS so that every global access is coalesced:
+//   1. the batch sizes and orders are loaded with consecutive lanes on
+//      consecutive batches, and each batch's tile count and cost (32-bit: at
+//      most 2^24 tiles and 2^25 * 56 cost units for a 2^31-argument batch) are
+//      written to LDS;
+//   2. thread t reads its kScanPer consecutive batches back and keeps them in
+//      registers; thread totals are scanned within each wave by lane
+//      shuffles and across the waves in LDS;
+//   3. the two 64-bit prefix arrays are staged, one after the other, in the
+//      same LDS buffer and written out by consecutive lanes.
+// Tiles are powers of two (1 << tile_shift arguments), so every count is an
+// add and a shift.
 constexpr int kScanPer = 8;
+constexpr int kScanRound = kScanThreads * kScanPer;
 __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__restrict__ bn,
                                                                const int32_t *__restrict__ bk,
                                                                int32_t nbatch, int tile_shift,
                                                                int64_t *__restrict__ tile_start,
                                                                int64_t *__restrict__ cost_start) {
   constexpr int kWaves = kScanThreads / 64;
+  // One 64 KB buffer: the per-batch counts (two 32-bit arrays) in step 1,
+  // then each 64-bit prefix array in turn in step 3.
+  __shared__ __attribute__((aligned(16))) int64_t s_buf[kScanRound];
   __shared__ int64_t s_t[kWaves], s_c[kWaves];
+  uint32_t *const s_nt = reinterpret_cast<uint32_t *>(s_buf);
+  uint32_t *const s_nc = s_nt + kScanRound;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int64_t round_up = (int64_t(1) << tile_shift) - 1;
+  const uint32_t round_up = (uint32_t(1) << tile_shift) - 1;
   int64_t carry_t = 0, carry_c = 0;  // totals of the earlier rounds
-  for (int32_t base = 0; base < nbatch; base += kScanThreads * kScanPer) {
-    const int32_t first = base + tid * kScanPer;
-    int64_t ct[kScanPer], cc[kScanPer];
+  for (int32_t base = 0; base < nbatch; base += kScanRound) {
+    const int32_t m = nbatch - base < kScanRound ? nbatch - base : kScanRound;
+    const int32_t *const bnr = bn + base;
+    const int32_t *const bkr = bk + base;
+    // 1. Coalesced loads from indices clamped into the table (all in flight
+    // together); batches past the end count as empty.
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-      // Unconditional loads from an index clamped into the table, so all of
-      // them are in flight together; batches past the end count as empty.
-      const int32_t b = first + i;
-      const int32_t bc = b < nbatch ? b : nbatch - 1;
-      const int32_t nr = bn[bc];
-      const int kr = bk[bc];
-      const int64_t n = b < nbatch && nr > 0 ? nr : 0;
-      ct[i] = (n + round_up) >> tile_shift;
-      cc[i] = ((n + 63) >> 6) * pass_cost(clamp_order(kr));
+      const int j = i * kScanThreads + tid;
+      const uint32_t jc = uint32_t(j < m ? j : m - 1);
+      const int32_t nr = bnr[jc];
+      const int kr = bkr[jc];
+      const uint32_t n = j < m && nr > 0 ? uint32_t(nr) : 0u;
+      s_nt[j] = (n + round_up) >> tile_shift;
+      s_nc[j] = ((n + 63u) >> 6) * uint32_t(pass_cost(clamp_order(kr)));
+    }
+    __syncthreads();
+    // 2. Thread t owns batches kScanPer*t .. kScanPer*t + kScanPer-1.
+    uint32_t ct[kScanPer], cc[kScanPer];
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      ct[i] = s_nt[tid * kScanPer + i];
+      cc[i] = s_nc[tid * kScanPer + i];
     }
     int64_t st = 0, sc = 0;
 #pragma unroll
@@ -127,7 +149,7 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
       s_t[wv] = it;
       s_c[wv] = ic;
     }
-    __syncthreads();
+    __syncthreads();  // also: every thread has read its counts from s_buf
     int64_t tot_t = 0, tot_c = 0;
     for (int w = 0; w < kWaves; ++w) {
       if (w < wv) {
@@ -137,18 +159,33 @@ __global__ __launch_bounds__(kScanThreads) void ws_scan_kernel(const int32_t *__
       tot_t += s_t[w];
       tot_c += s_c[w];
     }
-    __syncthreads();  // s_t, s_c are rewritten by the next round
-    int64_t rt = carry_t + it - st, rc = carry_c + ic - sc;  // exclusive
+    // 3. Exclusive prefixes, staged in LDS and stored by consecutive lanes.
+    int64_t r = carry_t + it - st;
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-      const int32_t b = first + i;
-      if (b < nbatch) {
-        tile_start[b] = rt;
-        cost_start[b] = rc;
-      }
-      rt += ct[i];
-      rc += cc[i];
+      s_buf[tid * kScanPer + i] = r;
+      r += ct[i];
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const int j = i * kScanThreads + tid;
+      if (j < m) tile_start[base + uint32_t(j)] = s_buf[j];
+    }
+    __syncthreads();
+    r = carry_c + ic - sc;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      s_buf[tid * kScanPer + i] = r;
+      r += cc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const int j = i * kScanThreads + tid;
+      if (j < m) cost_start[base + uint32_t(j)] = s_buf[j];
+    }
+    __syncthreads();  // s_buf, s_t and s_c are rewritten by the next round
     carry_t += tot_t;
     carry_c += tot_c;
   }
