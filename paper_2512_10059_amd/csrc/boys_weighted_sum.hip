@@ -398,8 +398,11 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
           const uint64_t mC = __ballot(isC) & valid;
           const int rA = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mA >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mA), 0u)));
           const int rC = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mC >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mC), 0u)));
-          slot[it] = isA ? bA + rA : (isC ? bC + rC : bB + (lane - rA - rC));
-          if (kFull || it * 64 + lane < count) s_x[wv][slot[it]] = xv[it];
+          // Lanes past the tile's end take slot 0: their rank in B would count
+          // them past the tile, and the slot is read again before the store.
+          const bool in = kFull || it * 64 + lane < count;
+          slot[it] = !in ? 0 : (isA ? bA + rA : (isC ? bC + rC : bB + (lane - rA - rC)));
+          if (in) s_x[wv][slot[it]] = xv[it];
           const int cA = __popcll(mA), cC = __popcll(mC);
           const int cV = kFull ? 64 : __popcll(valid);
           bA += cA;
