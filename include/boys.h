@@ -173,7 +173,8 @@ BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
                                    double tol, double *out, hipStream_t stream);
 
 /*
- * Times every tile/unroll configuration of the persistent kernel on these
+ * Times every configuration of the persistent kernel (tile length, region
+ * binning on or off, grid of 1 to 3 rounds of resident workgroups) on these
  * arguments (each run writes out), keeps the fastest for later
  * boys_weighted_sum calls on this device, and reports it.  Synchronises
  * `stream`.  best_config (may be NULL) receives the configuration index,
