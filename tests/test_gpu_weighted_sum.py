@@ -263,3 +263,23 @@ def test_partial_tiles_write_only_their_batch(config):
     for b in range(n.size):
         inside[off[b]:off[b] + n[b]] = True
     assert np.all(out[~inside] == sentinel)
+
+
+@pytest.mark.parametrize("nb", [1, 8191, 8192, 8193, 16384])
+def test_batch_counts_around_scan_rounds(nb):
+    """The cost scan takes the batch table in rounds of 8192 entries: one
+    batch, one short of a round, exactly one and two rounds, and one entry
+    into a second round, with sizes 0..9 (empty batches included), every
+    argument against the oracle."""
+    rng = np.random.default_rng(31 + nb)
+    n = rng.integers(0, 10, nb).astype(np.int32)
+    if nb == 1:
+        n[0] = 7
+    off = np.concatenate([[0], np.cumsum(n[:-1])]).astype(np.int64)
+    k = rng.integers(0, 33, nb).astype(np.int32)
+    w_off = np.concatenate([[0], np.cumsum(k[:-1] + 1)]).astype(np.int64)
+    w = rng.standard_normal(int((k + 1).sum()))
+    x = workloads.gaussian_pair_arguments(int(n.sum()), seed=32)
+    bt = workloads.Batches(x=x, batch_off=off, batch_n=n, batch_kmax=k, w=w, w_off=w_off)
+    out = boys.boys_weighted_sum(*to_dev(bt)).cpu().numpy()
+    check(bt, out)
