@@ -385,7 +385,13 @@ def cpu_baseline_leg(torch, wo, fp32, screen=None):
         xs = fp32["_x32"][:1 << 20].cpu().numpy().astype(np.float64)
         ref = oracle.boys(xs, 16, threads=threads)
         got = fp32["_o32"][:1 << 20].cpu().numpy().astype(np.float64)
-        res["fp32_max_abs_err_on_2^20"] = float(np.abs(got - ref).max())
+        row_err = np.abs(got - ref).max(axis=1)
+        res["fp32_max_abs_err_on_2^20"] = float(row_err.max())
+        from paper_2512_10059_amd.tables import f32_region_bounds
+        x0f, x1f = f32_region_bounds()
+        regions = {"A'": xs < x0f, "B'": (xs >= x0f) & (xs < x1f), "C'": xs >= x1f}
+        res["fp32_max_abs_err_per_region"] = {
+            name: float(row_err[m].max()) if m.any() else None for name, m in regions.items()}
     log(f"cpu baseline: {res['value']:.3e} values/s on {threads} threads; GPU max err {err:.2e}")
     return res
 

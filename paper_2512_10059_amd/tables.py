@@ -24,3 +24,10 @@ def f64_region_a_degrees():
     n = [int(v) for v in re.findall(r"-?\d+", _define(h, "BOYS_RA_DEG_N_INIT"))]
     m = [int(v) for v in re.findall(r"-?\d+", _define(h, "BOYS_RA_DEG_M_INIT"))]
     return list(zip(n, m))
+
+
+def f32_region_bounds():
+    """(x0', x1') of the FP32 path, as the kernels hold them (FP32 values):
+    A' = [0, x0'), B' = [x0', x1'), C' = [x1', inf)."""
+    h = os.path.join(_CSRC, "boys_coeffs_f32.h")
+    return tuple(float.fromhex(_define(h, name).strip().rstrip("f")) for name in ("BOYS_F32_X0", "BOYS_F32_X1"))

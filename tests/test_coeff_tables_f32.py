@@ -196,3 +196,11 @@ def test_emulated_fp32_path_within_1e6(K):
     ref = oracle.boys(xs.astype(np.float64), K)
     err = np.abs(got - ref)
     assert err.max() <= TOL, f"K={K}: {err.max():.3e}"
+
+
+def test_package_reads_the_fp32_region_bounds():
+    """The host helper that splits reported errors by region reads the same
+    x0' and x1' as the kernels compile in."""
+    from paper_2512_10059_amd.tables import f32_region_bounds
+    x0, x1 = f32_region_bounds()
+    assert F32(x0) == X0F and F32(x1) == X1F and x0 == float(X0F) and x1 == float(X1F)
