@@ -275,6 +275,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Waves per workgroup of the persistent kernel.  Every wave is an
+// independent worker with its own LDS slice, so the workgroup only groups
+// waves for dispatch: a workgroup's slot on a CU is freed when its last wave
+// ends.
+constexpr int kWsWaves = 4;
+constexpr int kWsBlock = 64 * kWsWaves;
+
 // Persistent kernel in which every wave is an independent worker: wave gw of
 // W takes the tiles whose cost prefix lies in [gw, gw+1) * total / W.  A tile
 // is 64*ITEMS arguments of one batch.  With BIN the wave sorts its tile by
@@ -282,13 +289,13 @@ __device__ __forceinline__ void wave_sync() {
 // each 64-lane pass over the sorted tile runs a single region path except at
 // the two region boundaries.  No workgroup barrier follows the set-up.
 template <int ITEMS, bool BIN, class TS>
-__global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
+__global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
   static_assert((ITEMS & (ITEMS - 1)) == 0, "tiles are powers of two: the scan counts them by shifts");
   constexpr int T = 64 * ITEMS;
-  __shared__ wpair s_down[kWavesPerBlock][kTableLen];  // (w_l, 1/(2l+1))
-  __shared__ wpair s_up[kWavesPerBlock][kTableLen];    // (w_{l+1}, 2l+1)
-  __shared__ double s_x[kWavesPerBlock][BIN ? T : 1];  // sorted arguments, then their results
-  __shared__ __attribute__((aligned(16))) double s_asym[kWavesPerBlock][kAsymTableLen];  // w_l a_l
+  __shared__ wpair s_down[kWsWaves][kTableLen];  // (w_l, 1/(2l+1))
+  __shared__ wpair s_up[kWsWaves][kTableLen];    // (w_{l+1}, 2l+1)
+  __shared__ double s_x[kWsWaves][BIN ? T : 1];  // sorted arguments, then their results
+  __shared__ __attribute__((aligned(16))) double s_asym[kWsWaves][kAsymTableLen];  // w_l a_l
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -308,8 +315,8 @@ __global__ __launch_bounds__(kBlock) void ws_kernel(WsArgs a) {
   wpair *const up = &s_up[wv][kPad];
   double w0 = 0.0, wk = 0.0;  // w_0 and w_k of the current batch
 
-  const int64_t gw = int64_t(blockIdx.x) * kWavesPerBlock + wv;
-  const int64_t W = int64_t(gridDim.x) * kWavesPerBlock;
+  const int64_t gw = int64_t(blockIdx.x) * kWsWaves + wv;
+  const int64_t W = int64_t(gridDim.x) * kWsWaves;
   const int64_t total = uniform(a.cost_start[a.nbatch]);
   const int64_t lo = total * gw / W;
   const int64_t hi = total * (gw + 1) / W;
@@ -644,11 +651,11 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set) {
   const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
   int resident = 0;
   BOYS_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern),
-                                                            kBlock, 0));
+                                                            kWsBlock, 0));
   if (resident < 1) resident = 1;
   mp.gridDim = dim3(unsigned(s.cus * resident * conf.rounds));
   mp.func = reinterpret_cast<void *>(kern);
-  mp.blockDim = dim3(kBlock);
+  mp.blockDim = dim3(kWsBlock);
   mp.sharedMemBytes = 0;
   mp.kernelParams = main_args;
   mp.extra = nullptr;
