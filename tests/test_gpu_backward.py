@@ -156,3 +156,35 @@ def test_full_differentiation_workload_sampled():
     assert np.all(np.abs(gs - oracle.central_difference(x[idx], G[idx])) <= tol + 1e-12 * S)
     Fs = F.detach()[torch.from_numpy(idx).to(DEV)].cpu().numpy()
     assert np.abs(Fs - oracle.boys(x[idx], 16)).max() <= EPS_TOL
+
+
+def _around(points, steps=2):
+    out = []
+    for p in points:
+        v = p
+        for _ in range(steps):
+            v = np.nextafter(v, -np.inf) if v > 0 else v
+        for _ in range(2 * steps + 1):
+            out.append(v)
+            v = np.nextafter(v, np.inf)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("kmax", [16, 36])
+def test_domain_values_and_region_boundaries(kmax):
+    """Outside the domain the gradient is NaN (x < 0, NaN) or zero (x = +inf,
+    where every F_{k+1} is 0).  At the region boundaries of both table sets
+    (the paper's x0, x1 for orders up to 32; the high-order set's for 33..40,
+    which kmax 36 recomputes at order 37), +-2 ulps, the gradient matches
+    the oracle within the bound of the other tests."""
+    rng = np.random.default_rng(77 + kmax)
+    pts = _around([0.0, 5e-324, 11.899848152108484, 28.98933773882074,
+                   14.842842360917231, 30.455574446774907, 1e300])
+    x = np.concatenate([pts, [-1.0, -1e-300, np.nan, np.inf]])
+    G = rng.standard_normal((x.size, kmax + 1))
+    g = gpu_backward(x, G)
+    m = pts.size
+    assert np.all(np.isnan(g[m:m + 3])), g[m:m + 3]
+    assert g[m + 3] == 0.0
+    S, tol = bounds(pts, G[:m])
+    assert np.all(np.abs(g[:m] - oracle.backward(pts, G[:m])) <= tol)
