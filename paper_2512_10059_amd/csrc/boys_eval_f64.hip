@@ -24,11 +24,20 @@ namespace boys {
 namespace {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
-__device__ __forceinline__ void store_nt(T *p, T v) {
-  __builtin_nontemporal_store(v, p);
-}
+// Streaming stores: non-temporal, at device scope (the nt and sc1 bits of
+// the store).  The output is written once and read only after the kernel
+// ends.  Measured at 2^26 arguments and kmax 32: 2.84 ms per launch
+// (6.42 TB/s) against 3.07 ms with the non-temporal bit alone (what the
+// compiler's non-temporal store builtin sets), 2.98 ms with nt at workgroup
+// scope (sc0) and 3.26 ms at system scope without nt.  Only the buffer-store
+// builtin takes the scope bits, so a wave's 64 contiguous rows are written
+// through a buffer resource that spans exactly those rows: every offset is
+// inside it, and the compiler sees an ordinary store (its hazards and waits
+// included).
+constexpr int kStreamPolicy = 2 | 16;  // nt | sc1
+constexpr int kRawBufferFlags = 0x00020000;  // dword 3 of a raw gfx9 buffer resource
 
 // Waves per workgroup of the write-out kernel for order K.  The LDS stage
 // takes 64*(K+1)*8 bytes per wave; four-wave groups at orders above 32
@@ -48,7 +57,7 @@ __global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
   constexpr int WB = eval_waves(K);
   __shared__ __attribute__((aligned(16))) double stage[WB * 64 * CP];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the buffer base below
   double *slice = stage + wave * 64 * CP;
 
   for (int64_t blk = blockIdx.x; blk * (64 * WB) < n; blk += gridDim.x) {
@@ -62,7 +71,8 @@ __global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
     const int64_t rows = n - row0 < 64 ? n - row0 : 64;
     if (contiguous && rows == 64) {
       // The wave's 64 rows are 64*C contiguous doubles = 32*C 16-byte units.
-      d2 *dst = reinterpret_cast<d2 *>(out + row0 * C);
+      const __amdgpu_buffer_rsrc_t rows_rsrc =
+          __builtin_amdgcn_make_buffer_rsrc(out + row0 * C, 0, 64 * C * 8, kRawBufferFlags);
 #pragma unroll
       for (int j = 0; j < (32 * C + 63) / 64; ++j) {
         const int u = lane + 64 * j;
@@ -74,14 +84,15 @@ __global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
             const int r = (2 * u) / C, c = 2 * u - r * C;
             v = d2{slice[r * CP + c], slice[r * CP + c + 1]};
           }
-          store_nt(dst + u, v);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rows_rsrc, u * 16, 0,
+                                                 kStreamPolicy);
         }
       }
     } else if (rows > 0) {
       const int total = int(rows) * C;
       for (int e = lane; e < total; e += 64) {
         const int r = e / C, c = e - r * C;
-        store_nt(out + (row0 + r) * ld + c, slice[r * CP + c]);
+        __builtin_nontemporal_store(slice[r * CP + c], out + (row0 + r) * ld + c);
       }
     }
     __syncthreads();
