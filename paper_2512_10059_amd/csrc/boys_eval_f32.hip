@@ -20,14 +20,6 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-typedef unsigned u4 __attribute__((ext_vector_type(4)));
-
-// Streaming stores, non-temporal at device scope (nt | sc1), through a buffer
-// resource spanning exactly a wave's 64 contiguous rows, as in the FP64
-// write-out.
-constexpr int kStreamPolicy = 2 | 16;
-constexpr int kRawBufferFlags = 0x00020000;  // dword 3 of a raw gfx9 buffer resource
-
 template <int K>
 __global__ __launch_bounds__(kBlock) void eval_f32_kernel(const float *__restrict__ x, int64_t n,
                                                           float *__restrict__ out, int64_t ld,
@@ -36,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void eval_f32_kernel(const float *__restric
   constexpr int CP = (C % 2 == 0) ? C + 1 : C;  // LDS row stride (odd)
   __shared__ __attribute__((aligned(16))) float stage[kWavesPerBlock * 64 * CP];
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the buffer base below
+  const int wave = threadIdx.x >> 6;
   float *slice = stage + wave * 64 * CP;
 
   for (int64_t blk = blockIdx.x; blk * kBlock < n; blk += gridDim.x) {
@@ -50,8 +42,7 @@ __global__ __launch_bounds__(kBlock) void eval_f32_kernel(const float *__restric
     const int64_t rows = n - row0 < 64 ? n - row0 : 64;
     if (contiguous && rows == 64) {
       // 64*C floats = 16*C units of 16 bytes.
-      const __amdgpu_buffer_rsrc_t rows_rsrc =
-          __builtin_amdgcn_make_buffer_rsrc(out + row0 * C, 0, 64 * C * 4, kRawBufferFlags);
+      f4 *dst = reinterpret_cast<f4 *>(out + row0 * C);
 #pragma unroll
       for (int j = 0; j < (16 * C + 63) / 64; ++j) {
         const int u = lane + 64 * j;
@@ -66,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void eval_f32_kernel(const float *__restric
               v[t] = slice[r * CP + c];
             }
           }
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rows_rsrc, u * 16, 0, kStreamPolicy);
+          __builtin_nontemporal_store(v, dst + u);
         }
       }
     } else if (rows > 0) {
