@@ -434,16 +434,21 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
         }
       }
       wave_sync();
+      // Non-temporal stores: the output is not read again by the kernel.
+      // Measured on the batched workload: 0.2045-0.2109 ms per call against
+      // 0.2133-0.2137 ms with plain stores (nt sc1: 0.2092-0.2098 ms).
       char *const to = reinterpret_cast<char *>(a.out + first);
       if (count == T) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it)
-          *reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)) = s_x[wv][slot[it]];
+          __builtin_nontemporal_store(s_x[wv][slot[it]],
+                                      reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)));
       } else {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
           const double v = s_x[wv][slot[it]];
-          if (it * 64 + lane < count) *reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)) = v;
+          if (it * 64 + lane < count)
+            __builtin_nontemporal_store(v, reinterpret_cast<double *>(to + (lane8 + uint32_t(it) * 512u)));
         }
       }
       wave_sync();
