@@ -19,6 +19,11 @@ quantities the hot path produces:
 * :func:`pairsum`         z_i = sum_l c_l sum_j F_l(x_i + x_j) y_j, the paper's
                           benchmark quantity (Sec. III, Algorithm 2), for
                           selected rows i.
+
+Pins: ``tests/oracle_pins.py`` ties the long-double F_k to mpmath, quadrature
+and the closed forms; ``tests/oracle_composition_pins.py`` ties each composed
+quantity above to values built from mpmath's incomplete gamma function (not
+from this module's F), with planted mistakes in this file that must be caught.
 """
 from __future__ import annotations
 
