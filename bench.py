@@ -353,6 +353,18 @@ def leg_high(torch, boys, workloads, steps, warmup, dev, wo=None):
     return res
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(torch, wo, fp32, screen=None):
     """The oracle on the first 2^25 write-out arguments (half the workload,
     about 20 thread-seconds of CPU work), all host cores; the GPU rows of the
@@ -374,9 +386,17 @@ def cpu_baseline_leg(torch, wo, fp32, screen=None):
         if screen is not None:
             got = screen["_out"][s:s + chunk].cpu().numpy()
             err_screen = max(err_screen, float(np.abs(got - ref).max()))
+    # The same oracle on one thread, over the first 2^20 of those arguments.
+    m1 = 1 << 20
+    t0 = time.perf_counter()
+    oracle.boys(wo["x_host"][:m1], 32, threads=1)
+    t_one = time.perf_counter() - t0
     res = {"value": m * 33 / t_cpu, "unit": "values/s", "cores": threads, "kind": "oracle",
            "sample": f"first 2^25 of the 2^26 write-out arguments, kmax=32, long-double oracle, "
                      f"{threads} threads, {t_cpu:.1f} s wall ({t_cpu * threads:.0f} thread-s)",
+           "cpu_model": cpu_model(),
+           "value_1_thread": m1 * 33 / t_one,
+           "sample_1_thread": f"first 2^20 of the same arguments on one thread, {t_one:.1f} s",
            "gpu_max_abs_err_on_sample": err}
     if screen is not None:
         res["screen_max_abs_err_on_sample"] = err_screen
@@ -392,7 +412,8 @@ def cpu_baseline_leg(torch, wo, fp32, screen=None):
         regions = {"A'": xs < x0f, "B'": (xs >= x0f) & (xs < x1f), "C'": xs >= x1f}
         res["fp32_max_abs_err_per_region"] = {
             name: float(row_err[m].max()) if m.any() else None for name, m in regions.items()}
-    log(f"cpu baseline: {res['value']:.3e} values/s on {threads} threads; GPU max err {err:.2e}")
+    log(f"cpu baseline: {res['value']:.3e} values/s on {threads} threads "
+        f"({res['value_1_thread']:.3e} on one); GPU max err {err:.2e}")
     return res
 
 

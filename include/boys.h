@@ -8,7 +8,9 @@
  * (Vikhamar-Sandberg and Repisky, "Efficient Boys function evaluation using
  * minimax approximation", arXiv 2512.10059, Sec. I eq. 3) with the paper's
  * method (Sec. II F, Algorithm 1): the axis is split into A = [0, x0),
- * B = [x0, x1) and C = [x1, inf).  On A a rational minimax approximant
+ * B = [x0, x1] and C = (x1, inf).  (The paper's region equation leaves the
+ * end at x1 open to reading; here x = x1 is evaluated in B, on whose closed
+ * interval r_B was fitted.)  On A a rational minimax approximant
  * r_{A,k} gives F_k and the downward recurrence the lower orders; on B the
  * approximant r_B gives F_0 and the upward recurrence the higher orders; on C
  * the asymptotic form sqrt(pi)/(2 sqrt x) and its upward recurrence are used.
@@ -34,7 +36,14 @@
  *    results are within 1e-6.
  *  - The library keeps lazily created workspaces per device (the batched
  *    entry points' prefix arrays and cached graphs, the pair sums' sort
- *    buffers); boys_finalize() releases them.
+ *    buffers); boys_finalize() releases them.  A workspace that has to grow
+ *    is replaced by a larger one and the old one is kept until
+ *    boys_finalize(), since work already enqueued may still read it: no
+ *    call waits on the device.  The entry points that keep such state
+ *    (boys_weighted_sum(_tol), boys_tune_weighted_sum, boys_pairsum(_tol))
+ *    return BOYS_ECAPTURE, enqueueing nothing, when `stream` is under graph
+ *    capture; boys_weighted_sum_noalloc is the batched entry point for
+ *    captured streams.
  *  - Calls are thread-safe with respect to each other except that two
  *    concurrent batched calls (boys_weighted_sum, boys_weighted_sum_tol), or
  *    two concurrent pair-sum calls, on one device share a workspace and must
@@ -61,7 +70,9 @@ enum {
     BOYS_EINVAL = -1,   /* bad argument: null pointer, size, order or stride */
     BOYS_EHIP = -2,     /* a HIP runtime call failed */
     BOYS_ENOTSUP = -3,  /* the current device is not supported (needs gfx950) */
-    BOYS_ENOMEM = -4    /* the workspace could not be allocated */
+    BOYS_ENOMEM = -4,   /* the workspace could not be allocated */
+    BOYS_ECAPTURE = -5  /* a call that keeps a cached workspace or graph was made
+                           on a stream under graph capture (nothing enqueued) */
 };
 
 /* Highest order of the paper's FP64 tables (every FP64 entry point), of the
@@ -153,7 +164,8 @@ BOYS_API int boys_eval_f32(const float *x, int64_t n, int kmax, float *out, int6
  * element: out-of-range orders are clamped to 0..32 in the kernel, and
  * batches must not overlap in out.
  * Errors: BOYS_EINVAL for a null pointer with nbatch > 0 or nbatch out of
- * range; BOYS_ENOMEM if the workspace cannot grow.
+ * range; BOYS_ENOMEM if the workspace cannot grow; BOYS_ECAPTURE on a
+ * stream under graph capture.
  */
 BOYS_API int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
                       const int32_t *batch_kmax, const double *w, const int64_t *w_off,
@@ -238,7 +250,8 @@ BOYS_API int boys_backward_tol(const double *x, const double *grad_f, int64_t n,
  * scattered back), which needs a per-device workspace of about 32 n bytes
  * plus sort scratch, allocated on first use and grown when n grows.
  * Errors: BOYS_EINVAL for bad sizes, orders, null or overlapping pointers;
- * BOYS_ENOMEM if the workspace cannot grow.
+ * BOYS_ENOMEM if the workspace cannot grow; BOYS_ECAPTURE on a stream under
+ * graph capture.
  */
 BOYS_API int boys_pairsum(const double *x, const double *y, int64_t n, const double *c, int kmax,
                           double *z, hipStream_t stream);

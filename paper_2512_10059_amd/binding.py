@@ -104,6 +104,9 @@ def _rows(out: torch.Tensor, n: int, ncol: int, dtype, device, name: str) -> int
         raise BoysError(f"{name} must be a {dtype} tensor on {device}")
     if out.dim() != 2 or out.shape[0] != n or out.shape[1] < ncol or (n > 0 and out.stride(1) != 1):
         raise BoysError(f"{name} must have shape ({n}, >={ncol}) with unit column stride")
+    if n > 1 and out.stride(0) < ncol:
+        raise BoysError(f"{name} rows overlap (row stride {out.stride(0)} < {ncol}); "
+                        "pass a contiguous tensor")
     return out.stride(0) if n > 1 else max(out.shape[1], ncol)
 
 
@@ -292,7 +295,11 @@ class BoysFunction(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         grad_x = None
         if ctx.needs_input_grad[0]:
-            g = grad_f if grad_f.stride(1) == 1 else grad_f.contiguous()
+            # An upstream gradient may be a broadcast view (row stride 0, e.g.
+            # from F.sum(0) @ v); the kernel needs disjoint rows.
+            rows_ok = grad_f.stride(1) == 1 and (grad_f.shape[0] <= 1 or
+                                                 grad_f.stride(0) >= grad_f.shape[1])
+            g = grad_f if rows_ok else grad_f.contiguous()
             grad_x = boys_backward(x, g, ctx.kmax, tol=ctx.tol)
         return grad_x, None, None
 

@@ -18,6 +18,12 @@ int hip_status(hipError_t err);
 // (cached per device), BOYS_EHIP if the device cannot be queried.
 int check_device();
 
+// BOYS_OK when `stream` is not under graph capture, BOYS_ECAPTURE when it is
+// (capturing or invalidated), BOYS_EHIP if the query fails.  The entry points
+// that keep a per-device workspace or cached graph refuse captured streams:
+// their workspace may have to grow, and a graph replayed later would share it.
+int check_not_capturing(hipStream_t stream);
+
 // Frees the workspaces of boys_pairsum on every device (boys_finalize).
 void pairsum_release_all();
 

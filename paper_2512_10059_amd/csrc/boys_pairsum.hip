@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <vector>
 #include <utility>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -184,6 +185,9 @@ struct PairState {
   std::mutex mu;
   void *buf = nullptr;
   size_t bytes = 0;
+  // Buffers replaced by larger ones; work already enqueued may still use
+  // them, so they are freed only by boys_finalize (after a device sync).
+  std::vector<void *> retired;
 };
 constexpr int kMaxDevices = 64;
 PairState g_pair[kMaxDevices];
@@ -198,10 +202,12 @@ void pairsum_release_all() {
   for (int d = 0; d < kMaxDevices; ++d) {
     PairState &s = g_pair[d];
     std::lock_guard<std::mutex> lock(s.mu);
-    if (!s.buf) continue;
+    if (!s.buf && s.retired.empty()) continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     (void)hipDeviceSynchronize();
-    (void)hipFree(s.buf);
+    if (s.buf) (void)hipFree(s.buf);
+    for (void *old : s.retired) (void)hipFree(old);
+    s.retired.clear();
     s.buf = nullptr;
     s.bytes = 0;
   }
@@ -225,6 +231,7 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   if (!x || !y || !c || !z) return BOYS_EINVAL;
   if (overlaps(z, n * 8, x, n * 8) || overlaps(z, n * 8, y, n * 8)) return BOYS_EINVAL;
   if (int st = check_device()) return st;
+  if (int st = check_not_capturing(stream)) return st;
   int dev = 0;
   BOYS_TRY_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
@@ -268,17 +275,20 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   const size_t off_ys = off_idx + align256(4 * un);
   const size_t off_zs = off_ys + align256(8 * un);
   const size_t off_tmp = off_zs + align256(8 * un);
-  const size_t need = off_tmp + align256(sort_bytes);
+  size_t need = off_tmp + align256(sort_bytes);
 
   PairState &s = g_pair[dev];
   std::lock_guard<std::mutex> lock(s.mu);
+  const size_t old_bytes = s.bytes;
   if (s.bytes < need) {
     if (s.buf) {
-      BOYS_TRY_HIP(hipDeviceSynchronize());
-      BOYS_TRY_HIP(hipFree(s.buf));
+      // Earlier calls may still be using it: retire it rather than wait.
+      s.retired.push_back(s.buf);
       s.buf = nullptr;
       s.bytes = 0;
     }
+    // Grow geometrically, so the retired buffers stay below the current one.
+    need = need > 2 * old_bytes ? need : 2 * old_bytes;
     if (hipMalloc(&s.buf, need) != hipSuccess) {
       (void)hipGetLastError();
       s.buf = nullptr;

@@ -41,6 +41,13 @@ int check_device() {
   return ok ? BOYS_OK : BOYS_ENOTSUP;
 }
 
+int check_not_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t err = hipStreamIsCapturing(stream, &cs);
+  if (err != hipSuccess) return hip_status(err);
+  return cs == hipStreamCaptureStatusNone ? BOYS_OK : BOYS_ECAPTURE;
+}
+
 }  // namespace boys
 
 extern "C" {
@@ -52,6 +59,7 @@ const char *boys_strerror(int status) {
     case BOYS_EHIP: return "HIP runtime error";
     case BOYS_ENOTSUP: return "device not supported (libboys needs gfx950)";
     case BOYS_ENOMEM: return "workspace allocation failed";
+    case BOYS_ECAPTURE: return "stream is under graph capture (this entry point keeps cached workspaces and graphs)";
     default: return "unknown status";
   }
 }

@@ -34,6 +34,7 @@
 #include <cstring>
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "boys.h"
 #include "boys_common.hpp"
@@ -524,10 +525,26 @@ struct GraphSlot {
   bool has_key = false;
 };
 
+// A graph replaced by a newer one.  Its launches may still be queued, so it is
+// destroyed once an event recorded behind them (on the stream of the call
+// that replaced it: calls on one device are ordered by the caller) has
+// completed, checked without waiting at later calls.
+struct RetiredGraph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipEvent_t done;
+};
+
 struct DeviceState {
   std::mutex mu;
   int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
   int64_t ws_cap = 0;
+  // Workspaces replaced by larger ones.  Graphs already enqueued may still
+  // read them, so they are freed only by boys_finalize (which synchronises
+  // the device); capacities double, so together they stay below the current
+  // one.
+  std::vector<int64_t *> retired;
+  std::vector<RetiredGraph> retired_graphs;
   GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
   int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
@@ -535,13 +552,15 @@ struct DeviceState {
     for (const auto &row : slot)
       for (const GraphSlot &g : row)
         if (g.exec || g.graph) return true;
-    return false;
+    return !retired_graphs.empty();
   }
 };
 
 constexpr int kMaxDevices = 64;
 DeviceState g_dev[kMaxDevices];
 
+// Destroys a slot's graph at once: for graphs never launched, or after a
+// device synchronisation.
 void drop_slot(GraphSlot &g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -550,9 +569,58 @@ void drop_slot(GraphSlot &g) {
   g.has_key = false;
 }
 
+// Moves a slot's graph to the retired list behind an event recorded on
+// `stream`; if the event cannot be made, waits for the stream instead.
+int retire_slot(DeviceState &s, GraphSlot &g, hipStream_t stream) {
+  if (!g.exec && !g.graph) return BOYS_OK;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, stream) != hipSuccess) {
+    if (ev) (void)hipEventDestroy(ev);
+    BOYS_TRY_HIP(hipStreamSynchronize(stream));
+    drop_slot(g);
+    return BOYS_OK;
+  }
+  s.retired_graphs.push_back(RetiredGraph{g.graph, g.exec, ev});
+  g.exec = nullptr;
+  g.graph = nullptr;
+  g.has_key = false;
+  return BOYS_OK;
+}
+
+int retire_graphs(DeviceState &s, hipStream_t stream) {
+  for (auto &row : s.slot)
+    for (GraphSlot &g : row)
+      if (int st = retire_slot(s, g, stream)) return st;
+  return BOYS_OK;
+}
+
+// Destroys the retired graphs whose event has completed (never waits).
+void reap_graphs(DeviceState &s) {
+  size_t keep = 0;
+  for (RetiredGraph &r : s.retired_graphs) {
+    if (hipEventQuery(r.done) == hipSuccess) {
+      (void)hipGraphExecDestroy(r.exec);
+      (void)hipGraphDestroy(r.graph);
+      (void)hipEventDestroy(r.done);
+    } else {
+      s.retired_graphs[keep++] = r;
+    }
+  }
+  s.retired_graphs.resize(keep);
+  (void)hipGetLastError();  // a query of a pending event reports hipErrorNotReady
+}
+
+// After a device synchronisation: destroys every graph.
 void drop_graphs(DeviceState &s) {
   for (auto &row : s.slot)
     for (GraphSlot &g : row) drop_slot(g);
+  for (RetiredGraph &r : s.retired_graphs) {
+    (void)hipGraphExecDestroy(r.exec);
+    (void)hipGraphDestroy(r.graph);
+    (void)hipEventDestroy(r.done);
+  }
+  s.retired_graphs.clear();
 }
 
 // Configuration from the tuning cache file named by BOYS_TUNE_CACHE (lines
@@ -594,17 +662,17 @@ struct Call {
 };
 
 // Makes sure the workspace holds 2*(nbatch+1) entries.
-int ensure_workspace(DeviceState &s, int32_t nbatch) {
+int ensure_workspace(DeviceState &s, int32_t nbatch, hipStream_t stream) {
   const int64_t need = int64_t(nbatch) + 1;
   if (s.ws_cap >= need) return BOYS_OK;
   if (s.ws) {
-    // An earlier graph may still be reading the old workspace.
-    BOYS_TRY_HIP(hipDeviceSynchronize());
-    BOYS_TRY_HIP(hipFree(s.ws));
+    // An earlier graph may still be reading the old workspace: retire it
+    // rather than wait for the device.
+    s.retired.push_back(s.ws);
     s.ws = nullptr;
     s.ws_cap = 0;
   }
-  drop_graphs(s);
+  if (int st = retire_graphs(s, stream)) return st;
   int64_t cap = 1024;
   while (cap < need) cap *= 2;
   if (hipMalloc(&s.ws, size_t(2 * cap) * sizeof(int64_t)) != hipSuccess) {
@@ -617,7 +685,7 @@ int ensure_workspace(DeviceState &s, int32_t nbatch) {
 }
 
 // Builds (or reuses) the graph {scan -> persistent kernel} for this call.
-int prepare_graph(DeviceState &s, const Call &c, int cfg, int set) {
+int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t stream) {
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   const void *p[7] = {c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out};
@@ -628,7 +696,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set) {
   key.ws = s.ws;
   GraphSlot &g = s.slot[set][cfg];
   if (g.has_key && g.exec && key == g.key) return BOYS_OK;
-  drop_slot(g);
+  if (int st = retire_slot(s, g, stream)) return st;
 
   const WsConfig &conf = kConfigs[cfg];
   int64_t *tile_start = s.ws;
@@ -696,9 +764,10 @@ int device_state(DeviceState **out) {
 // Enqueues one evaluation with configuration cfg and table set `set` (state
 // lock held).
 int launch(DeviceState &s, const Call &c, int cfg, int set, hipStream_t stream) {
-  if (int st = ensure_workspace(s, c.nbatch)) return st;
-  if (int st = prepare_graph(s, c, cfg, set)) {
-    drop_slot(s.slot[set][cfg]);
+  if (!s.retired_graphs.empty()) reap_graphs(s);
+  if (int st = ensure_workspace(s, c.nbatch, stream)) return st;
+  if (int st = prepare_graph(s, c, cfg, set, stream)) {
+    drop_slot(s.slot[set][cfg]);  // built here, never launched
     return st;
   }
   BOYS_TRY_HIP(hipGraphLaunch(s.slot[set][cfg].exec, stream));
@@ -709,6 +778,7 @@ int weighted_sum_with_set(const Call &c, int set, hipStream_t stream) {
   if (int st = validate(c)) return st;
   if (c.nbatch == 0) return BOYS_OK;
   if (int st = check_device()) return st;
+  if (int st = check_not_capturing(stream)) return st;
   DeviceState *s = nullptr;
   if (int st = device_state(&s)) return st;
   std::lock_guard<std::mutex> lock(s->mu);
@@ -748,6 +818,7 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   if (int st = validate(c)) return st;
   if (nbatch == 0) return BOYS_OK;
   if (int st = check_device()) return st;
+  if (int st = check_not_capturing(stream)) return st;
   DeviceState *s = nullptr;
   if (int st = device_state(&s)) return st;
   std::lock_guard<std::mutex> lock(s->mu);
@@ -824,11 +895,13 @@ void boys_finalize(void) {
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState &s = g_dev[d];
     std::lock_guard<std::mutex> lock(s.mu);
-    if (!s.ws && !s.has_graphs()) continue;
+    if (!s.ws && !s.has_graphs() && s.retired.empty()) continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     (void)hipDeviceSynchronize();
     drop_graphs(s);
     if (s.ws) (void)hipFree(s.ws);
+    for (int64_t *old : s.retired) (void)hipFree(old);
+    s.retired.clear();
     s.ws = nullptr;
     s.ws_cap = 0;
   }

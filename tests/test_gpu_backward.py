@@ -127,6 +127,23 @@ def test_autograd_matches_kernel_and_oracle():
     assert np.abs(F.detach().cpu().numpy() - Fo).max() <= EPS_TOL
 
 
+def test_autograd_broadcast_upstream_gradient():
+    """A loss (F.sum(0) @ v) whose upstream gradient reaches BoysFunction as a
+    broadcast view (row stride 0): the gradient is -sum_k v_k F_{k+1}(x) per
+    argument, as the oracle gives for G = v in every row."""
+    x, _ = workloads.backward_workload(n=4000, kmax=16, seed=31)
+    v = np.random.default_rng(32).standard_normal(17)
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    F = boys.BoysFunction.apply(xt, 16)
+    (F.sum(0) @ torch.from_numpy(v).to(DEV)).backward()
+    G = np.broadcast_to(v, (x.size, 17))
+    S, tol = bounds(x, G)
+    assert np.all(np.abs(xt.grad.cpu().numpy() - oracle.backward(x, np.ascontiguousarray(G))) <= tol)
+    # The direct entry point refuses overlapping rows instead of misreading them.
+    with pytest.raises(boys.BoysError):
+        boys.boys_backward(xt.detach(), torch.from_numpy(v).to(DEV).expand(x.size, 17), 16)
+
+
 def test_empty_and_invalid():
     x = torch.empty(0, dtype=torch.float64, device=DEV)
     G = torch.empty((0, 17), dtype=torch.float64, device=DEV)

@@ -81,6 +81,30 @@ def test_invalid_arguments_raise():
         boys.boys_pairsum(x, x, np.ones(42))  # kmax 41
 
 
+def test_workspace_growth_and_capture_status():
+    """A call that grows the workspace enqueued right behind a smaller one
+    (the old buffer is retired, not waited for): both results are right.
+    On a stream under graph capture the call is refused with nothing
+    enqueued."""
+    boys.finalize()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+    x1, y1, c1 = workloads.pair_workload(n=300, kmax=12, seed=41)
+    x2, y2, c2 = workloads.pair_workload(n=3000, kmax=12, seed=42)
+    z1 = boys.boys_pairsum(t(x1), t(y1), c1)
+    z2 = boys.boys_pairsum(t(x2), t(y2), c2)
+    check(x1, y1, c1, z1.cpu().numpy(), np.arange(x1.size))
+    check(x2, y2, c2, z2.cpu().numpy(), np.arange(0, x2.size, 7))
+    xd, yd = t(x1), t(y1)
+    out = torch.zeros_like(xd)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(boys.BoysError, match="capture"):
+        with torch.cuda.graph(g):
+            boys.boys_pairsum(xd, yd, c1, out=out)
+    torch.cuda.synchronize()
+    assert not out.any()
+
+
 def test_high_orders_take_the_high_set_for_any_tolerance():
     x, y, c = workloads.pair_workload(n=700, kmax=38, seed=77, x_max=40.0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
