@@ -172,6 +172,28 @@ BOYS_API int boys_weighted_sum(const double *x, const int64_t *batch_off, const 
                       int32_t nbatch, double *out, hipStream_t stream);
 
 /*
+ * boys_weighted_sum for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, same kernels and the same result, bit for bit,
+ * as boys_weighted_sum (the paper's tables, the configuration chosen for
+ * boys_weighted_sum).  The scan's prefix arrays live in a fixed device array
+ * of 2 (BOYS_NOALLOC_MAX_BATCHES + 1) int64 (1 MiB), one copy per device,
+ * held until the process ends; the two kernels are launched directly on
+ * `stream` (no cached graph), so the call enqueues only kernel launches and
+ * may be captured.  Calls that overlap on one device share that array and
+ * race: order them (same stream, or synchronised).  The first call on a
+ * device looks up the array's address and the kernels' occupancy; make it
+ * outside a capture.
+ * Errors: as boys_weighted_sum, and BOYS_EINVAL for
+ * nbatch > BOYS_NOALLOC_MAX_BATCHES.
+ */
+#define BOYS_NOALLOC_MAX_BATCHES 65536
+BOYS_API int boys_weighted_sum_noalloc(const double *x, const int64_t *batch_off,
+                                       const int32_t *batch_n, const int32_t *batch_kmax,
+                                       const double *w, const int64_t *w_off, int32_t nbatch,
+                                       double *out, hipStream_t stream);
+
+/*
  * boys_weighted_sum with the table set chosen by tol as in boys_eval_f64_tol:
  * tol >= 1e-10 takes the screening set (per argument |error| <= 1e-10
  * sum_l |w_l| plus rounding), 5e-14 <= tol < 1e-10 the paper's tables (the

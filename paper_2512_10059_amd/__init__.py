@@ -12,6 +12,7 @@ from __future__ import annotations
 
 _BINDING_NAMES = {
     "BoysError", "BoysFunction", "boys_eval_f64", "boys_eval_f64_tol", "boys_eval_f32", "boys_weighted_sum",
+    "boys_weighted_sum_noalloc",
     "boys_tune_weighted_sum", "boys_backward", "boys_pairsum", "weighted_sum_config_name",
     "weighted_sum_num_configs", "weighted_sum_get_config", "weighted_sum_set_config",
     "finalize", "lib", "library_path", "F64_KMAX", "F64_KMAX_EVAL", "F64_KMAX_BACKWARD", "F32_KMAX",

@@ -34,6 +34,7 @@ _SIGNATURES = {
     "boys_eval_f32": ([_P, _I64, _INT, _P, _I64, _P], _INT),
     "boys_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P], _INT),
     "boys_weighted_sum_tol": ([_P, _P, _P, _P, _P, _P, _I32, ctypes.c_double, _P, _P], _INT),
+    "boys_weighted_sum_noalloc": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P], _INT),
     "boys_backward_tol": ([_P, _P, _I64, _INT, _I64, ctypes.c_double, _P, _P], _INT),
     "boys_tune_weighted_sum": ([_P, _P, _P, _P, _P, _P, _I32, _P, _P,
                                 ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_float)], _INT),
@@ -184,6 +185,21 @@ def boys_weighted_sum(x, batch_off, batch_n, batch_kmax, w, w_off, out=None,
         else:
             _check(lib().boys_weighted_sum_tol(*args, float(tol), _ptr(out), _stream(x.device)),
                    "boys_weighted_sum_tol")
+    return out
+
+
+def boys_weighted_sum_noalloc(x, batch_off, batch_n, batch_kmax, w, w_off,
+                              out: torch.Tensor) -> torch.Tensor:
+    """boys_weighted_sum through the entry point that allocates nothing (fixed
+    per-device scratch, kernels launched directly; capturable).  ``out`` is
+    required, so that this wrapper allocates nothing either."""
+    nb = _batch_args(x, batch_off, batch_n, batch_kmax, w, w_off)
+    _vector(out, torch.float64, "out")
+    with torch.cuda.device(x.device):
+        _check(lib().boys_weighted_sum_noalloc(_ptr(x), _ptr(batch_off), _ptr(batch_n),
+                                               _ptr(batch_kmax), _ptr(w), _ptr(w_off), nb,
+                                               _ptr(out), _stream(x.device)),
+               "boys_weighted_sum_noalloc")
     return out
 
 

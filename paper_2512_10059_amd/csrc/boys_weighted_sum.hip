@@ -548,6 +548,8 @@ struct DeviceState {
   GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
   int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
+  int resident[2][kNumConfigs] = {};  // workgroups per CU, 0: not queried yet
+  int64_t *scratch_ptr = nullptr;      // this device's copy of `scratch`
   bool has_graphs() const {
     for (const auto &row : slot)
       for (const GraphSlot &g : row)
@@ -684,6 +686,22 @@ int ensure_workspace(DeviceState &s, int32_t nbatch, hipStream_t stream) {
   return BOYS_OK;
 }
 
+// Grid of the persistent kernel: `rounds` rounds of the workgroups that fit
+// on every CU at once.
+int main_grid(DeviceState &s, int cfg, int set, unsigned *grid) {
+  const WsConfig &conf = kConfigs[cfg];
+  int &resident = s.resident[set][cfg];
+  if (resident == 0) {
+    const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
+    int r = 0;
+    BOYS_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, reinterpret_cast<const void *>(kern),
+                                                              kWsBlock, 0));
+    resident = r < 1 ? 1 : r;
+  }
+  *grid = unsigned(s.cus * resident * conf.rounds);
+  return BOYS_OK;
+}
+
 // Builds (or reuses) the graph {scan -> persistent kernel} for this call.
 int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t stream) {
   GraphKey key;
@@ -722,11 +740,9 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t s
   void *main_args[] = {&args};
   hipKernelNodeParams mp = {};
   const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
-  int resident = 0;
-  BOYS_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern),
-                                                            kWsBlock, 0));
-  if (resident < 1) resident = 1;
-  mp.gridDim = dim3(unsigned(s.cus * resident * conf.rounds));
+  unsigned grid = 0;
+  if (int st = main_grid(s, cfg, set, &grid)) return st;
+  mp.gridDim = dim3(grid);
   mp.func = reinterpret_cast<void *>(kern);
   mp.blockDim = dim3(kWsBlock);
   mp.sharedMemBytes = 0;
@@ -786,10 +802,66 @@ int weighted_sum_with_set(const Call &c, int set, hipStream_t stream) {
   return launch(*s, c, s->config, set, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant (boys_weighted_sum_noalloc): the scan's two prefix
+// arrays live in a fixed device array instead of the grown workspace, and the
+// two kernels are launched directly on the caller's stream instead of through
+// a cached graph, so the call allocates nothing and can be captured.  Every
+// call's scan rewrites all prefix entries the main kernel then reads, so
+// nothing has to be cleared between calls; calls that overlap on one device
+// share the array and race.
+constexpr int32_t kNoAllocMaxBatches = BOYS_NOALLOC_MAX_BATCHES;
+__device__ __align__(256) int64_t scratch[2 * (int64_t(kNoAllocMaxBatches) + 1)];
+
+// This device's address of `scratch` (looked up once per device, with the
+// device current; the array's name is only a host-side stand-in).
+int scratch_address(DeviceState &s, int64_t **out) {
+  if (!s.scratch_ptr) {
+    void *p = nullptr;
+    BOYS_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    s.scratch_ptr = static_cast<int64_t *>(p);
+  }
+  *out = s.scratch_ptr;
+  return BOYS_OK;
+}
+
+int launch_direct(DeviceState &s, const Call &c, int cfg, int64_t *tile_start, int64_t *cost_start,
+                  hipStream_t stream) {
+  const WsConfig &conf = kConfigs[cfg];
+  const int tile_shift = __builtin_ctz(unsigned(64 * conf.items));
+  unsigned grid = 0;
+  if (int st = main_grid(s, cfg, 0, &grid)) return st;
+  hipLaunchKernelGGL(ws_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, c.bn, c.bk, c.nbatch,
+                     tile_shift, tile_start, cost_start);
+  BOYS_TRY_HIP(hipGetLastError());
+  const WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
+  hipLaunchKernelGGL(conf.kernel, dim3(grid), dim3(kWsBlock), 0, stream, args);
+  BOYS_TRY_HIP(hipGetLastError());
+  return BOYS_OK;
+}
+
 }  // namespace
 }  // namespace boys
 
 extern "C" {
+
+int boys_weighted_sum_noalloc(const double *x, const int64_t *batch_off, const int32_t *batch_n,
+                              const int32_t *batch_kmax, const double *w, const int64_t *w_off,
+                              int32_t nbatch, double *out, hipStream_t stream) {
+  using namespace boys;
+  const Call c{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out};
+  if (nbatch > kNoAllocMaxBatches) return BOYS_EINVAL;
+  if (int st = validate(c)) return st;
+  if (nbatch == 0) return BOYS_OK;
+  if (int st = check_device()) return st;
+  DeviceState *s = nullptr;
+  if (int st = device_state(&s)) return st;
+  std::lock_guard<std::mutex> lock(s->mu);
+  int64_t *base = nullptr;
+  if (int st = scratch_address(*s, &base)) return st;
+  const int cfg = s->config < 0 ? kDefaultConfig : s->config;
+  return launch_direct(*s, c, cfg, base, base + (int64_t(kNoAllocMaxBatches) + 1), stream);
+}
 
 int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
                       const int32_t *batch_kmax, const double *w, const int64_t *w_off,

@@ -77,6 +77,12 @@ def test_argument_errors_without_gpu(lib):
     assert w(*([dummy] * 6), (1 << 24) + 1, dummy, None) == EINVAL
     assert w(None, *([dummy] * 5), 3, dummy, None) == EINVAL
     assert w(*([None] * 6), 0, None, None) == 0
+    na = lib.boys_weighted_sum_noalloc
+    na.argtypes = [P] * 6 + [ctypes.c_int32, P, P]
+    assert na(*([dummy] * 6), 65536 + 1, dummy, None) == EINVAL  # beyond its fixed scratch
+    assert na(*([dummy] * 6), -1, dummy, None) == EINVAL
+    assert na(None, *([dummy] * 5), 3, dummy, None) == EINVAL
+    assert na(*([None] * 6), 0, None, None) == 0
     lib.boys_weighted_sum_set_config.argtypes = [I]
     assert lib.boys_weighted_sum_set_config(999) == EINVAL
     assert lib.boys_weighted_sum_num_configs() > 1
