@@ -71,6 +71,63 @@ __device__ __forceinline__ double exp_neg(double x) {
   return __builtin_amdgcn_ldexp(p, -int(nd));
 }
 
+// The address of a constant table, hidden from the optimiser: reads through
+// it stay scalar loads instead of being folded back into literals (two scalar
+// moves each) from the table's known initializer.
+#define BOYS_CONST_AS __attribute__((address_space(4)))
+template <class P>
+__device__ __forceinline__ const BOYS_CONST_AS P *opaque(const P *p) {
+  auto q = (const BOYS_CONST_AS P *)(p);
+  asm("" : "+s"(q));
+  return q;
+}
+
+// The same routine with its constants read from constant memory by scalar
+// loads (a few wide loads per evaluation instead of two scalar moves per
+// literal) for the batched consumer, whose issue slots the moves compete for.
+struct ExpConsts {
+  double inv_ln2, ln2_hi, ln2_lo, pad;
+  double taylor[kExpDegree + 1];
+};
+static __constant__ const ExpConsts kExpConsts = {BOYS_EXP_INV_LN2, BOYS_EXP_LN2_HI, BOYS_EXP_LN2_LO,
+                                                  0.0, BOYS_EXP_TAYLOR_INIT};
+
+__device__ __forceinline__ double exp_neg_loaded(double x) {
+  const BOYS_CONST_AS ExpConsts &c = *opaque(&kExpConsts);
+  const double nd = __builtin_rint(x * c.inv_ln2);
+  double r = __builtin_fma(nd, c.ln2_hi, -x);
+  r = __builtin_fma(nd, c.ln2_lo, r);
+  double p = add_uniform(r * c.taylor[kExpDegree], c.taylor[kExpDegree - 1]);
+#pragma unroll
+  for (int j = kExpDegree - 2; j >= 0; --j) p = fma_uniform_addend(p, r, c.taylor[j]);
+  return __builtin_amdgcn_ldexp(p, -int(nd));
+}
+
+// 1/x for finite x in the normal range: the hardware reciprocal refined by
+// two Newton steps (within about one ulp).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// p/q for the rationals' denominators, which are positive and far from the
+// ends of the exponent range on every interval the method uses them: the
+// reciprocal of q from recip() and one correction of the quotient,
+//     y = p r,  y' = y + r (p - q y),
+// whose residual p - q y is exact under the fused multiply-add, so y' is the
+// quotient to within about half an ulp plus r's error times the residual.
+// Against the IEEE division sequence this drops the scaling and fix-up steps
+// (8 instructions instead of 11), which only matter near overflow, underflow
+// and for special operands; NaN still propagates.
+__device__ __forceinline__ double div_positive(double p, double q) {
+  const double r = recip(q);
+  const double y = p * r;
+  return __builtin_fma(__builtin_fma(-q, y, p), r, y);
+}
+
 // ---------------------------------------------------------------------------
 // r_{A,K} and r_B of a table set T at a compile-time order (the pair kernel
 // and region B).  The coefficients are indexed as compile-time constants, so
@@ -179,6 +236,18 @@ __device__ __forceinline__ double rational_loaded(double x, const double *P, con
   return p / q;
 }
 
+// As rational_loaded, with div_positive for the quotient.
+template <int NP, int NQ, class Ptr>
+__device__ __forceinline__ double rational_loaded_pos(double x, Ptr P, Ptr Q) {
+  double p = P[NP];
+#pragma unroll
+  for (int i = NP - 1; i >= 0; --i) p = fma_uniform_addend(p, x, P[i]);
+  double q = Q[NQ];
+#pragma unroll
+  for (int i = NQ - 1; i >= 0; --i) q = fma_uniform_addend(q, x, Q[i]);
+  return div_positive(p, q);
+}
+
 template <class T = PaperTables>
 __device__ __forceinline__ double rational_a_rt(double x, int k) {
   using R = RtRows<T>;
@@ -187,6 +256,42 @@ __device__ __forceinline__ double rational_a_rt(double x, int k) {
   const double *Q = rows.q[k];
   if (k < kSplitK) return rational_loaded<R::pad_n, R::pad_m>(x, P, Q);
   return rational_loaded<R::pad_n, R::hi_m>(x, P, Q);
+}
+
+// r_{A,k}(x) for a runtime k with div_positive (the batched consumer).
+template <class T = PaperTables>
+__device__ __forceinline__ double rational_a_rt_pos(double x, int k) {
+  using R = RtRows<T>;
+  const R &rows = rt_rows<T>();
+  const double *P = rows.p[k];
+  const double *Q = rows.q[k];
+  if (k < kSplitK) return rational_loaded_pos<R::pad_n, R::pad_m>(x, P, Q);
+  return rational_loaded_pos<R::pad_n, R::hi_m>(x, P, Q);
+}
+
+// r_B of a table set, its coefficients read from constant memory with scalar
+// loads (a few wide loads instead of two scalar moves per literal).
+template <class T>
+struct RbRow {
+  double p[T::rb_n + 1];
+  double q[T::rb_m + 1];
+};
+template <class T>
+constexpr RbRow<T> make_rb_row() {
+  RbRow<T> r{};
+  for (int i = 0; i <= T::rb_n; ++i) r.p[i] = T::rb_p[i];
+  for (int i = 0; i <= T::rb_m; ++i) r.q[i] = T::rb_q[i];
+  return r;
+}
+static __constant__ const RbRow<PaperTables> kRbRow = make_rb_row<PaperTables>();
+static __constant__ const RbRow<ScreenTables> kRbRowScreen = make_rb_row<ScreenTables>();
+
+template <class T>
+__device__ __forceinline__ double rational_b_pos(double x) {
+  const BOYS_CONST_AS RbRow<T> *r;
+  if constexpr (std::is_same_v<T, ScreenTables>) r = opaque(&kRbRowScreen);
+  else r = opaque(&kRbRow);
+  return rational_loaded_pos<T::rb_n, T::rb_m>(x, r->p, r->q);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,61 +309,102 @@ constexpr double kAsymCoefHost[kAsymOrders] = BOYS_ASYM_COEF_INIT;
 static __constant__ const double kAsymCoef[kAsymOrders] = BOYS_ASYM_COEF_INIT;
 static_assert(kAsymOrders == kF64Kmax + 1, "one coefficient per order");
 
-// Weighted sums for the batched consumer, with the sum accumulated inside the
-// recurrence as in the paper's benchmark consumer (Sec. III, Algorithm 2).
-//
-// The recurrences run in chunks of kChunk steps whose LDS reads are issued
-// together, so a chunk waits for LDS once.  Each step needs a weight and a
-// step constant; the per-wave tables hold them as adjacent pairs, one
-// 16-byte LDS read per step:
-//   down[l] = (w_l, 1/(2l+1))        for the downward pass,
-//   up[l]   = (w_{l+1}, 2l+1)        for the upward pass.
-// The tables are padded so that chunks may overrun the order: the weight is
-// 0 for l < 0 and l > k, which makes the extra steps add exactly zero (their
-// F values stay finite for finite x).  Valid indices: -kPad .. kF64Kmax+kPad.
-typedef double wpair __attribute__((ext_vector_type(2)));
-constexpr int kChunk = 4;
-constexpr int kPad = kChunk;
-constexpr int kTableLen = kF64Kmax + 1 + 2 * kPad;
+// (2l-1)!! and 1/(2l-1)!!, l = 0..32, for the weight sweeps below.
+static __constant__ const double kDFact[kF64Kmax + 1] = BOYS_DFACT_INIT;
+static __constant__ const double kInvDFact[kF64Kmax + 1] = BOYS_INV_DFACT_INIT;
 
-// Region A: r_{A,k}, then F_l = (2x F_{l+1} + e^-x) * (1/(2l+1)) downwards.
-template <class T = PaperTables>
-__device__ __forceinline__ double wsum_region_a(double x, int k, double wk, const wpair *down) {
-  const double e = exp_neg(x);
-  const double two_x = x + x;
-  double F = rational_a_rt<T>(x, k);
-  double acc = wk * F;
-  for (int l0 = k - 1; l0 >= 0; l0 -= kChunk) {
-    wpair t[kChunk];
-#pragma unroll
-    for (int s = 0; s < kChunk; ++s) t[s] = down[l0 - s];
-#pragma unroll
-    for (int s = 0; s < kChunk; ++s) {
-      F = __builtin_fma(two_x, F, e) * t[s].y;
-      acc = __builtin_fma(t[s].x, F, acc);
-    }
-  }
-  return acc;
+// Weighted sums for the batched consumer.  The recurrences of Algorithm 1
+// are linear in their seed S (r_{A,k} or r_B) and in e^-x, so the weighted
+// sum the paper's benchmark accumulates inside the recurrence (Sec. III,
+// Algorithm 2) equals u S + v e^-x, and u and v follow from sweeping the
+// weights against the direction of the recurrence, substituting one order at
+// a time; neither S nor e^-x is needed until the end.
+//
+// Region A (downward, F_l = c_l (2x F_{l+1} + e^-x), c_l = 1/(2l+1)): after
+// substituting F_0..F_{s-1}, sum = u_s F_s + v_s e^-x + sum_{l>s} w_l F_l with
+//     u_0 = w_0, v_0 = 0,  u_{s+1} = w_{s+1} + 2x c_s u_s,  v_{s+1} = v_s + c_s u_s.
+// With z_s = u_s (2s-1)!!/(2k-1)!! each step is two fused multiply-adds,
+//     v_{s+1} = v_s + z_s (2k-1)!!/(2s+1)!!,
+//     z_{s+1} = 2x z_s + w_{s+1} (2s+1)!!/(2k-1)!!,
+// and sum = z_k S + v_k e^-x.
+// Region B (upward, F_{l+1} = g ((2l+1) F_l - e^-x), g = 1/(2x)): from the top,
+//     u_k = w_k, v_k = 0,  u_{l-1} = w_{l-1} + (2l-1) g u_l,  v_{l-1} = v_l - g u_l,
+// and with z_l = u_l (2l-1)!!, v' = v/g:
+//     v'_{l-1} = v'_l - z_l / (2l-1)!!,   z_{l-1} = g z_l + w_{l-1} (2l-3)!!,
+// and sum = z_0 S + g v'_0 e^-x.
+// The per-order constants sit in per-wave LDS tables of pairs, one 16-byte
+// read per step, formed when a wave enters a batch.  Both sweeps are padded to whole chunks of CH steps by zero entries
+// on the side they start from, where they leave z and v at exactly 0.
+// Rounding: in region A, u_s is a weighted sum of products of the positive
+// factors 2x c_l and the recurrence's own terms, so every step's rounding
+// reaches the result as at most a few ulps of sum_l |w_l| F_l, as in the
+// recurrence; in region B the sweep's terms are at most (2l-1)!!/(2x)^l <= 1
+// times F_0 from x0 on (the recurrence does not amplify there), so its
+// absolute error is a few (k+1) ulps of F_0 sum_l |w_l|, and an error in S
+// propagates exactly as through the recurrence.
+typedef double wpair __attribute__((ext_vector_type(2)));
+constexpr int kPolyOrders = BOYS_POLY_ORDERS;
+static_assert(kPolyOrders == kF64Kmax + 1, "one constant per order");
+constexpr int kChunkMax = 8;                          // longest sweep chunk of any configuration
+constexpr int kSweepPadA = kChunkMax;                 // zero entries below s = 0
+constexpr int kSweepLenA = kSweepPadA + kF64Kmax + 1; // entries s = -8..32
+constexpr int kSweepLenB = kF64Kmax + kChunkMax;      // entries l = 1..40
+
+// h t + c as VOP3 v_fma_f64 with its own destination.  The compiler's
+// builtin becomes v_fmac_f64, which accumulates into the addend's register:
+// in a chain over loaded constants that leaves the chain in a different
+// register each step and costs a move per chain and chunk.
+__device__ __forceinline__ double fma_step(double h, double t, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(h), "v"(t), "v"(c));
+  return r;
 }
 
-// Region B: r_B, then F_{l+1} = ((2l+1) F_l - e^-x) / (2x) upwards.
-template <class T = PaperTables>
-__device__ __forceinline__ double wsum_region_b(double x, int k, double w0, const wpair *up) {
-  const double e = exp_neg(x);
-  const double inv_2x = 0.5 / x;
-  double F = rational_b_t<T>(x);
-  double acc = w0 * F;
-  for (int l0 = 0; l0 < k; l0 += kChunk) {
-    wpair t[kChunk];
+// Region A.  ta[kSweepPadA + s] = (w_s (2s-1)!!/(2k-1)!!, (2k-1)!!/(2s-1)!!)
+// for 1 <= s <= k, (w_0/(2k-1)!!, 0) for s = 0, zeros for s < 0.
+template <int CH, class T = PaperTables>
+__device__ __forceinline__ double wsum_sweep_a(double x, int k, const wpair *ta) {
+  const double e = exp_neg_loaded(x);
+  const double S = rational_a_rt_pos<T>(x, k);
+  const double two_x = x + x;
+  const int steps = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
+  const wpair *t = ta + (kSweepPadA + k + 1 - steps);
+  double z = 0.0, v = 0.0;
+  for (int c0 = 0; c0 < steps; c0 += CH) {
+    wpair q[CH];
 #pragma unroll
-    for (int s = 0; s < kChunk; ++s) t[s] = up[l0 + s];
+    for (int s = 0; s < CH; ++s) q[s] = t[c0 + s];
 #pragma unroll
-    for (int s = 0; s < kChunk; ++s) {
-      F = __builtin_fma(t[s].y, F, -e) * inv_2x;
-      acc = __builtin_fma(t[s].x, F, acc);
+    for (int s = 0; s < CH; ++s) {  // z first: neither step reads the other's result
+      const double zs = z;
+      z = fma_step(two_x, zs, q[s].x);
+      v = fma_step(zs, q[s].y, v);
     }
   }
-  return acc;
+  return __builtin_fma(z, S, v * e);
+}
+
+// Region B.  tb[l-1] = (w_{l-1} (2l-3)!!, -1/(2l-1)!!) for 1 <= l <= k,
+// (w_k (2k-1)!!, 0) for l = k+1, zeros above.
+template <int CH, class T = PaperTables>
+__device__ __forceinline__ double wsum_sweep_b(double x, int k, const wpair *tb) {
+  const double e = exp_neg_loaded(x);
+  const double g = 0.5 * recip(x);
+  const double S = rational_b_pos<T>(x);
+  const int top = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
+  double z = 0.0, v = 0.0;
+  for (int l0 = top; l0 > 0; l0 -= CH) {
+    wpair q[CH];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) q[s] = tb[l0 - 1 - s];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {  // z first: neither step reads the other's result
+      const double zs = z;
+      z = fma_step(g, zs, q[s].x);
+      v = fma_step(zs, q[s].y, v);
+    }
+  }
+  return __builtin_fma(z, S, (g * v) * e);
 }
 
 // Region C: x^(-1/2) P(1/x) with P(g) = sum_l d_l g^l, d_l = w_l a_l.  The
@@ -266,8 +412,9 @@ __device__ __forceinline__ double wsum_region_b(double x, int k, double w0, cons
 // starts at k rounded up to a whole chunk, where the zeros above k leave P = 0
 // until d_k.  x^(-1/2) and 1/x come from one reciprocal square root r (1/x =
 // r^2, within a few ulps, which the asymptote's own 5e-14 bound dwarfs).
-constexpr int kAsymTableLen = kAsymOrders + 1;  // even: rows stay 16-byte aligned
+constexpr int kAsymTableLen = kF64Kmax + kChunkMax;  // zeros above k; even: 16-byte rows
 __device__ __forceinline__ double wsum_region_c(double x, int k, const double *asym) {
+  constexpr int kChunk = 4;
   const double r = ::rsqrt(x);
   const double g = r * r;
   const int top = (k + kChunk - 1) & ~(kChunk - 1);
@@ -275,10 +422,10 @@ __device__ __forceinline__ double wsum_region_c(double x, int k, const double *a
   for (int l0 = top - kChunk; l0 >= 0; l0 -= kChunk) {
     const wpair d01 = *reinterpret_cast<const wpair *>(&asym[l0]);
     const wpair d23 = *reinterpret_cast<const wpair *>(&asym[l0 + 2]);
-    P = __builtin_fma(P, g, d23.y);
-    P = __builtin_fma(P, g, d23.x);
-    P = __builtin_fma(P, g, d01.y);
-    P = __builtin_fma(P, g, d01.x);
+    P = fma_step(P, g, d23.y);
+    P = fma_step(P, g, d23.x);
+    P = fma_step(P, g, d01.y);
+    P = fma_step(P, g, d01.x);
   }
   return P * r;
 }

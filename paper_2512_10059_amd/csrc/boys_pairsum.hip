@@ -55,16 +55,6 @@ struct PairBPoly {
   double q[kHighKmax + 1];  // coefficients of Q (q[0] = 0)
 };
 
-// 1/x for finite x in the normal range: the hardware reciprocal refined by
-// two Newton steps (within about one ulp).
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 // sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region,
 // with the table set T.
 template <int K, class T>

@@ -62,7 +62,24 @@ struct WsArgs {
   const int64_t *tile_start;  // [nbatch+1]
   const int64_t *cost_start;  // [nbatch+1]
   int32_t nbatch;
+  int32_t taper;  // 0: equal shares per wave; p > 0: shares decreasing with the wave index
 };
+
+// Start of wave gw's share of the total cost among W waves.  Waves are
+// dispatched in index order, and a SIMD issues from its oldest waves first,
+// so the waves of a later round start late and, with equal shares, finish
+// last.  With taper p the shares follow F(u) = 1 - (1 - u)^p, u = gw/W:
+// the first waves take p times the mean share and the last ones almost
+// nothing, so the last round ends soon after the first ones.  Every wave
+// computes the boundaries with the same expression, so consecutive shares
+// meet exactly; the ends are exact (0 and total).
+__device__ __forceinline__ int64_t share_start(int64_t total, int64_t gw, int64_t W, int taper) {
+  if (!taper) return total * gw / W;
+  const double r = double(W - gw) / double(W);
+  double rp = r;
+  for (int i = 1; i < taper; ++i) rp *= r;
+  return total - int64_t(double(total) * rp);
+}
 
 __device__ __forceinline__ int clamp_order(int k) { return k < 0 ? 0 : (k > kF64Kmax ? kF64Kmax : k); }
 
@@ -214,29 +231,34 @@ __device__ __forceinline__ BatchFields load_batch(const WsArgs &a, int32_t b) {
   return f;
 }
 
-// Lane l's value of v, in a scalar register pair.
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
-  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
-  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
-}
-
-// Writes the weights w_0..w_k of a batch into the wave's tables (zeros above
-// k) and returns w_0 and w_k.  The loads use indices clamped to k, so they
-// are unconditional and in flight together.
-__device__ __forceinline__ void load_weights(const double *w, int k, int lane, wpair *down,
-                                             wpair *up, double *asym, double &w0, double &wk) {
-  const double wa = w[lane <= k ? lane : k];
-  const double wb = w[lane + 1 <= k ? lane + 1 : k];
-  if (lane <= kF64Kmax) {
-    const double wl = lane <= k ? wa : 0.0;
-    down[lane].x = wl;
-    up[lane].x = lane + 1 <= k ? wb : 0.0;
-    asym[lane] = wl * kAsymCoef[lane];
-  }
-  w0 = readlane_f64(wa, 0);
-  wk = readlane_f64(wa, k);
+// Forms the wave's LDS tables for a batch of order k with weights w (see the
+// weight sweeps in boys_device_f64_batched.hpp), one entry per lane; with
+// D_l = (2l-1)!!:
+//   ta[8 + s] = (w_s D_s / D_k, D_k / D_s)  1 <= s <= k;  (w_0 / D_k, 0) at s = 0;
+//   tb[l - 1] = (w_{l-1} (2l-3)!!, -1/(2l-1)!!)  1 <= l <= k;
+//               (w_k (2k-1)!!, 0) at l = k+1;
+//   tc[l]     = w_l a_l  l <= k  (region C);
+// zeros elsewhere.  The weight loads use indices clamped into the batch's
+// range, so they are unconditional and in flight together.
+__device__ __forceinline__ void load_tables(const double *w, int k, int lane, wpair *ta, wpair *tb,
+                                            double *tc) {
+  // Every load is unconditional, from an index clamped into its table; the
+  // entries outside their orders are zeroed by selects.
+  const int s = lane - kSweepPadA;  // ta's order
+  const int sc = s < 0 ? 0 : (s > k ? k : s);
+  const int lc = lane > k ? k : lane;  // tb's l - 1 and tc's l
+  const int lp = lane + 1 > k ? k : lane + 1;
+  const double ws = w[sc], wl = w[lc];
+  const double dfs = kDFact[sc], ids = kInvDFact[sc], dfl = kDFact[lc], idp = kInvDFact[lp];
+  const double al = kAsymCoef[lc];
+  const double dk = kDFact[k], idk = kInvDFact[k];
+  const bool in_a = s >= 0 && s <= k, in_b = lane <= k;
+  const wpair ea{in_a ? ws * (dfs * idk) : 0.0, in_a && s >= 1 ? ids * dk : 0.0};
+  const wpair eb{in_b ? wl * dfl : 0.0, lane + 1 <= k ? -idp : 0.0};
+  const double ec = in_b ? wl * al : 0.0;
+  if (lane < kSweepLenA) ta[lane] = ea;
+  if (lane < kSweepLenB) tb[lane] = eb;
+  if (lane < kAsymTableLen) tc[lane] = ec;
 }
 
 // Largest b in [0, nbatch] with cost_start[b] <= lo, searched by one wave:
@@ -288,15 +310,18 @@ constexpr int kWsBlock = 64 * kWsWaves;
 // is 64*ITEMS arguments of one batch.  With BIN the wave sorts its tile by
 // region (ballots and lane prefix counts, no atomics) into its LDS slice, so
 // each 64-lane pass over the sorted tile runs a single region path except at
-// the two region boundaries.  No workgroup barrier follows the set-up.
-template <int ITEMS, bool BIN, class TS>
+// the two region boundaries.  CH is the sweep chunk: the constant pairs of
+// CH orders are read together, so a chunk waits for LDS once.  No workgroup
+// barrier follows the set-up.
+template <int ITEMS, bool BIN, int CH, class TS>
 __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
   static_assert((ITEMS & (ITEMS - 1)) == 0, "tiles are powers of two: the scan counts them by shifts");
+  static_assert(CH <= kChunkMax, "the tables are padded for chunks up to kChunkMax");
   constexpr int T = 64 * ITEMS;
-  __shared__ wpair s_down[kWsWaves][kTableLen];  // (w_l, 1/(2l+1))
-  __shared__ wpair s_up[kWsWaves][kTableLen];    // (w_{l+1}, 2l+1)
+  __shared__ wpair s_ta[kWsWaves][kSweepLenA];  // region A's sweep constants
+  __shared__ wpair s_tb[kWsWaves][kSweepLenB];  // region B's sweep constants
   __shared__ double s_x[kWsWaves][BIN ? T : 1];  // sorted arguments, then their results
-  __shared__ __attribute__((aligned(16))) double s_asym[kWsWaves][kAsymTableLen];  // w_l a_l
+  __shared__ __attribute__((aligned(16))) double s_tc[kWsWaves][kAsymTableLen];  // w_l a_l: region C
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -305,22 +330,15 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
   // cost range, the batch fields and the order k in scalar registers, so
   // loops over k and the choice of r_A,k branch on scalar conditions.
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // Each wave fills its own tables: step constants now, weights per batch.
-  for (int t = lane; t < kTableLen; t += 64) {
-    const int l = t - kPad;
-    s_down[wv][t] = wpair{0.0, 1.0 / double(2 * l + 1)};
-    s_up[wv][t] = wpair{0.0, double(2 * l + 1)};
-  }
-  __syncthreads();  // the only block-wide barrier: waves work independently below
-  wpair *const down = &s_down[wv][kPad];
-  wpair *const up = &s_up[wv][kPad];
-  double w0 = 0.0, wk = 0.0;  // w_0 and w_k of the current batch
+  wpair *const ta = s_ta[wv];
+  wpair *const tb = s_tb[wv];
+  double *const tc = s_tc[wv];
 
   const int64_t gw = int64_t(blockIdx.x) * kWsWaves + wv;
   const int64_t W = int64_t(gridDim.x) * kWsWaves;
   const int64_t total = uniform(a.cost_start[a.nbatch]);
-  const int64_t lo = total * gw / W;
-  const int64_t hi = total * (gw + 1) / W;
+  const int64_t lo = uniform(share_start(total, gw, W, a.taper));
+  const int64_t hi = uniform(share_start(total, gw + 1, W, a.taper));
   int32_t b = uniform(wave_search(a.cost_start, a.nbatch, lo, lane));
   BatchFields f{};
   int64_t j = 0;
@@ -345,7 +363,8 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
     const int k = f.k;
     ++j;
     if (reload) {
-      load_weights(a.w + f.woff, k, lane, down, up, s_asym[wv], w0, wk);
+      wave_sync();  // the previous batch's passes have read the tables
+      load_tables(a.w + f.woff, k, lane, ta, tb, tc);
       reload = false;
     }
     // Argument loads: one wave-uniform base (the tile's first argument) and
@@ -380,8 +399,9 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
       // its class plus its rank in the class among the item's lanes, where
       // the ranks in A and C are lane-prefix counts of their masks and the
       // rank in B is the lane index minus both (valid lanes form a prefix).
-      // Each lane keeps the slots of its items; results are written back
-      // into them, then stored in the original order with coalesced stores.
+      // The slot is chosen by selects, not branches.  Each lane keeps the
+      // slots of its items; results are written back into them, then stored
+      // in the original order with coalesced stores.
       int nA = 0, nC = 0;
       int slot[ITEMS];
       auto bin = [&](auto full) {
@@ -406,11 +426,19 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
           const uint64_t mC = __ballot(isC) & valid;
           const int rA = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mA >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mA), 0u)));
           const int rC = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mC >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mC), 0u)));
-          // Lanes past the tile's end take slot 0: their rank in B would count
-          // them past the tile, and the slot is read again before the store.
-          const bool in = kFull || it * 64 + lane < count;
-          slot[it] = !in ? 0 : (isA ? bA + rA : (isC ? bC + rC : bB + (lane - rA - rC)));
-          if (in) s_x[wv][slot[it]] = xv[it];
+          int sl = isC ? bC + rC : bB + (lane - rA - rC);
+          sl = isA ? bA + rA : sl;
+          if constexpr (kFull) {
+            s_x[wv][sl] = xv[it];
+          } else {
+            // Lanes past the tile's end take slot 0: their rank in B would
+            // count them past the tile, and the slot is read again before the
+            // store.
+            const bool in = it * 64 + lane < count;
+            sl = in ? sl : 0;
+            if (in) s_x[wv][sl] = xv[it];
+          }
+          slot[it] = sl;
           const int cA = __popcll(mA), cC = __popcll(mC);
           const int cV = kFull ? 64 : __popcll(valid);
           bA += cA;
@@ -428,16 +456,14 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
         if (q < count) {
           const double xq = s_x[wv][q];
           double acc;
-          if (q < nA) acc = wsum_region_a<TS>(xq, k, wk, down);
-          else if (q < nAC) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b<TS>(xq, k, w0, up);
+          if (q < nA) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
+          else if (q < nAC) acc = wsum_region_c(xq, k, tc);
+          else acc = wsum_sweep_b<CH, TS>(xq, k, tb);
           s_x[wv][q] = acc;
         }
       }
       wave_sync();
       // Non-temporal stores: the output is not read again by the kernel.
-      // Measured on the batched workload: 0.2045-0.2109 ms per call against
-      // 0.2133-0.2137 ms with plain stores (nt sc1: 0.2092-0.2098 ms).
       char *const to = reinterpret_cast<char *>(a.out + first);
       if (count == T) {
 #pragma unroll
@@ -461,9 +487,9 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < TS::x0) acc = wsum_region_a<TS>(xq, k, wk, down);
-          else if (region_c<TS>(xq)) acc = wsum_region_c(xq, k, s_asym[wv]);
-          else acc = wsum_region_b<TS>(xq, k, w0, up);
+          if (xq < TS::x0) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
+          else if (region_c<TS>(xq)) acc = wsum_region_c(xq, k, tc);
+          else acc = wsum_sweep_b<CH, TS>(xq, k, tb);
           a.out[first + p] = acc;
         }
       }
@@ -482,28 +508,30 @@ struct WsConfig {
   WsKernel kernel_screen;  // the screening tables (eps_tol = 1e-10)
   int items;               // arguments per lane per tile (tile = 64 * items)
   int bin;                 // region binning in LDS
+  int chunk;               // sweep chunk (orders whose constants are read together)
   int rounds;              // grid = rounds x the workgroups resident per CU x CUs
+  int taper;               // per-wave shares decreasing with the wave index
   const char *name;
 };
 
-// Grids are counted in rounds of resident workgroups: the waves split the
-// cost evenly, so a partial last round leaves CUs idle while it runs.
-#define BOYS_WS_CONFIG(ITEMS, BIN, R, NAME) \
-  {&ws_kernel<ITEMS, BIN, PaperTables>, &ws_kernel<ITEMS, BIN, ScreenTables>, ITEMS, BIN, R, NAME}
+// Grids are counted in rounds of resident workgroups.
+#define BOYS_WS_CONFIG(ITEMS, BIN, CH, R, TAPER, NAME) \
+  {&ws_kernel<ITEMS, BIN, CH, PaperTables>, &ws_kernel<ITEMS, BIN, CH, ScreenTables>, ITEMS, BIN, CH, R, TAPER, NAME}
 const WsConfig kConfigs[] = {
-    BOYS_WS_CONFIG(4, true, 1, "wave-tile256-bin-1round"),
-    BOYS_WS_CONFIG(4, true, 2, "wave-tile256-bin-2rounds"),
-    BOYS_WS_CONFIG(4, true, 3, "wave-tile256-bin-3rounds"),
-    BOYS_WS_CONFIG(8, true, 1, "wave-tile512-bin-1round"),
-    BOYS_WS_CONFIG(8, true, 2, "wave-tile512-bin-2rounds"),
-    BOYS_WS_CONFIG(2, true, 2, "wave-tile128-bin-2rounds"),
-    BOYS_WS_CONFIG(4, false, 2, "wave-tile256-nobin-2rounds"),
-    BOYS_WS_CONFIG(2, false, 2, "wave-tile128-nobin-2rounds"),
-    BOYS_WS_CONFIG(8, true, 3, "wave-tile512-bin-3rounds"),
+    BOYS_WS_CONFIG(8, true, 4, 3, 2, "tile512-bin-ch4-3rounds-taper2"),
+    BOYS_WS_CONFIG(8, true, 4, 3, 0, "tile512-bin-ch4-3rounds"),
+    BOYS_WS_CONFIG(8, true, 4, 2, 2, "tile512-bin-ch4-2rounds-taper2"),
+    BOYS_WS_CONFIG(8, true, 4, 2, 3, "tile512-bin-ch4-2rounds-taper3"),
+    BOYS_WS_CONFIG(8, true, 4, 3, 3, "tile512-bin-ch4-3rounds-taper3"),
+    BOYS_WS_CONFIG(8, true, 4, 4, 3, "tile512-bin-ch4-4rounds-taper3"),
+    BOYS_WS_CONFIG(8, true, 8, 2, 2, "tile512-bin-ch8-2rounds-taper2"),
+    BOYS_WS_CONFIG(8, true, 8, 3, 3, "tile512-bin-ch8-3rounds-taper3"),
+    BOYS_WS_CONFIG(4, true, 4, 3, 2, "tile256-bin-ch4-3rounds-taper2"),
+    BOYS_WS_CONFIG(4, false, 4, 2, 0, "tile256-nobin-ch4-2rounds"),
 };
 #undef BOYS_WS_CONFIG
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
-constexpr int kDefaultConfig = 8;  // wave-tile512-bin-3rounds
+constexpr int kDefaultConfig = 0;  // tile512-bin-ch4-3rounds-taper2
 
 // ---------------------------------------------------------------------------
 // Per-device state: workspace, one cached graph per configuration (so the
@@ -537,19 +565,19 @@ struct RetiredGraph {
 
 struct DeviceState {
   std::mutex mu;
-  int64_t *ws = nullptr;  // tile_start then cost_start, each [cap]
+  void *ws = nullptr;  // see Workspace
   int64_t ws_cap = 0;
   // Workspaces replaced by larger ones.  Graphs already enqueued may still
   // read them, so they are freed only by boys_finalize (which synchronises
   // the device); capacities double, so together they stay below the current
   // one.
-  std::vector<int64_t *> retired;
+  std::vector<void *> retired;
   std::vector<RetiredGraph> retired_graphs;
   GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
   int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
   int resident[2][kNumConfigs] = {};  // workgroups per CU, 0: not queried yet
-  int64_t *scratch_ptr = nullptr;      // this device's copy of `scratch`
+  void *scratch_ptr = nullptr;         // this device's copy of `scratch`
   bool has_graphs() const {
     for (const auto &row : slot)
       for (const GraphSlot &g : row)
@@ -652,6 +680,21 @@ void store_config(int32_t nbatch, int cfg) {
   }
 }
 
+// The workspace of one call: the scan's prefix arrays of tiles and cost,
+// [cap] each (cap >= nbatch + 1), carved from one allocation or from
+// `scratch`.
+struct Workspace {
+  int64_t *tile_start;
+  int64_t *cost_start;
+};
+
+constexpr size_t workspace_bytes(int64_t cap) { return size_t(cap) * 2 * sizeof(int64_t); }
+
+Workspace carve(void *base, int64_t cap) {
+  int64_t *p = static_cast<int64_t *>(base);
+  return Workspace{p, p + cap};
+}
+
 struct Call {
   const double *x;
   const int64_t *boff;
@@ -663,7 +706,7 @@ struct Call {
   double *out;
 };
 
-// Makes sure the workspace holds 2*(nbatch+1) entries.
+// Makes sure the workspace holds nbatch + 1 entries.
 int ensure_workspace(DeviceState &s, int32_t nbatch, hipStream_t stream) {
   const int64_t need = int64_t(nbatch) + 1;
   if (s.ws_cap >= need) return BOYS_OK;
@@ -677,7 +720,7 @@ int ensure_workspace(DeviceState &s, int32_t nbatch, hipStream_t stream) {
   if (int st = retire_graphs(s, stream)) return st;
   int64_t cap = 1024;
   while (cap < need) cap *= 2;
-  if (hipMalloc(&s.ws, size_t(2 * cap) * sizeof(int64_t)) != hipSuccess) {
+  if (hipMalloc(&s.ws, workspace_bytes(cap)) != hipSuccess) {
     (void)hipGetLastError();
     s.ws = nullptr;
     return BOYS_ENOMEM;
@@ -717,8 +760,9 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t s
   if (int st = retire_slot(s, g, stream)) return st;
 
   const WsConfig &conf = kConfigs[cfg];
-  int64_t *tile_start = s.ws;
-  int64_t *cost_start = s.ws + s.ws_cap;
+  const Workspace ws = carve(s.ws, s.ws_cap);
+  int64_t *tile_start = ws.tile_start;
+  int64_t *cost_start = ws.cost_start;
   int tile_shift = __builtin_ctz(unsigned(64 * conf.items));  // items is a power of two
 
   BOYS_TRY_HIP(hipGraphCreate(&g.graph, 0));
@@ -736,7 +780,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t s
   sp.extra = nullptr;
   BOYS_TRY_HIP(hipGraphAddKernelNode(&scan_node, g.graph, nullptr, 0, &sp));
 
-  WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
+  WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch, conf.taper};
   void *main_args[] = {&args};
   hipKernelNodeParams mp = {};
   const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
@@ -811,30 +855,32 @@ int weighted_sum_with_set(const Call &c, int set, hipStream_t stream) {
 // nothing has to be cleared between calls; calls that overlap on one device
 // share the array and race.
 constexpr int32_t kNoAllocMaxBatches = BOYS_NOALLOC_MAX_BATCHES;
-__device__ __align__(256) int64_t scratch[2 * (int64_t(kNoAllocMaxBatches) + 1)];
+constexpr int64_t kNoAllocCap = int64_t(kNoAllocMaxBatches) + 1;
+static_assert(workspace_bytes(kNoAllocCap) % sizeof(int64_t) == 0, "whole int64 entries");
+__device__ __align__(256) int64_t scratch[workspace_bytes(kNoAllocCap) / sizeof(int64_t)];
 
 // This device's address of `scratch` (looked up once per device, with the
 // device current; the array's name is only a host-side stand-in).
-int scratch_address(DeviceState &s, int64_t **out) {
+int scratch_address(DeviceState &s, void **out) {
   if (!s.scratch_ptr) {
     void *p = nullptr;
     BOYS_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
-    s.scratch_ptr = static_cast<int64_t *>(p);
+    s.scratch_ptr = p;
   }
   *out = s.scratch_ptr;
   return BOYS_OK;
 }
 
-int launch_direct(DeviceState &s, const Call &c, int cfg, int64_t *tile_start, int64_t *cost_start,
-                  hipStream_t stream) {
+int launch_direct(DeviceState &s, const Call &c, int cfg, const Workspace &ws, hipStream_t stream) {
   const WsConfig &conf = kConfigs[cfg];
   const int tile_shift = __builtin_ctz(unsigned(64 * conf.items));
   unsigned grid = 0;
   if (int st = main_grid(s, cfg, 0, &grid)) return st;
   hipLaunchKernelGGL(ws_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, c.bn, c.bk, c.nbatch,
-                     tile_shift, tile_start, cost_start);
+                     tile_shift, ws.tile_start, ws.cost_start);
   BOYS_TRY_HIP(hipGetLastError());
-  const WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch};
+  const WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, ws.tile_start, ws.cost_start, c.nbatch,
+                    conf.taper};
   hipLaunchKernelGGL(conf.kernel, dim3(grid), dim3(kWsBlock), 0, stream, args);
   BOYS_TRY_HIP(hipGetLastError());
   return BOYS_OK;
@@ -857,10 +903,10 @@ int boys_weighted_sum_noalloc(const double *x, const int64_t *batch_off, const i
   DeviceState *s = nullptr;
   if (int st = device_state(&s)) return st;
   std::lock_guard<std::mutex> lock(s->mu);
-  int64_t *base = nullptr;
+  void *base = nullptr;
   if (int st = scratch_address(*s, &base)) return st;
   const int cfg = s->config < 0 ? kDefaultConfig : s->config;
-  return launch_direct(*s, c, cfg, base, base + (int64_t(kNoAllocMaxBatches) + 1), stream);
+  return launch_direct(*s, c, cfg, carve(base, kNoAllocCap), stream);
 }
 
 int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
@@ -972,7 +1018,7 @@ void boys_finalize(void) {
     (void)hipDeviceSynchronize();
     drop_graphs(s);
     if (s.ws) (void)hipFree(s.ws);
-    for (int64_t *old : s.retired) (void)hipFree(old);
+    for (void *old : s.retired) (void)hipFree(old);
     s.retired.clear();
     s.ws = nullptr;
     s.ws_cap = 0;

@@ -12,7 +12,14 @@ Pins, none of which reuses the generator's arithmetic:
   roundings damped by |r| <= ln2/2, truncation below 1e-17);
 * a_l = Gamma(l + 1/2)/2 is the double nearest (sqrt(pi)/2) prod_{m<l} (m + 1/2),
   the product taken exactly in rationals (the generator uses the gamma
-  function), and a_l x^(-l-1/2) reproduces the upward asymptote recurrence."""
+  function), and a_l x^(-l-1/2) reproduces the upward asymptote recurrence;
+* (2l-1)!! and 1/(2l-1)!! are the doubles nearest the exact integers and
+  rationals;
+* the batched consumer's weight sweeps (the kernel's table entries, padding
+  and operation order, emulated in FP64 with exact fused multiply-adds) give
+  sum_l w_l F_l to within their rounding bound for every order 0..32, with the
+  exact F_l from mpmath's incomplete gamma and the exact seed and e^-x, so a
+  mistake in the algebra shows as an O(1) error; planted mistakes fail."""
 import math
 import os
 import re
@@ -34,7 +41,8 @@ def load():
     return dict(inv_ln2=float.fromhex(d["BOYS_EXP_INV_LN2"]), ln2_hi=float.fromhex(d["BOYS_EXP_LN2_HI"]),
                 ln2_lo=float.fromhex(d["BOYS_EXP_LN2_LO"]), degree=int(d["BOYS_EXP_DEGREE"]),
                 taylor=vec("BOYS_EXP_TAYLOR_INIT"), asym=vec("BOYS_ASYM_COEF_INIT"),
-                asym_orders=int(d["BOYS_ASYM_ORDERS"]))
+                asym_orders=int(d["BOYS_ASYM_ORDERS"]), poly_orders=int(d["BOYS_POLY_ORDERS"]),
+                dfact=vec("BOYS_DFACT_INIT"), inv_dfact=vec("BOYS_INV_DFACT_INIT"))
 
 
 C = load()
@@ -218,3 +226,124 @@ def test_region_b_closed_form_check_detects_a_wrong_shift():
         s += c[l + 1] * F
     bad = mp.mpf(0.5) * mp.polyval(p[::-1], g) - e * mp.polyval(q_bad[::-1], g)
     assert abs(bad - s) > mp.mpf(10) ** -10
+
+
+# ---------------------------------------------------------------------------
+# The batched consumer's weight sweeps.
+
+X0, X1 = 11.899848152108484, 28.98933773882074
+
+
+def odd_dfact(l):
+    v = 1
+    for i in range(1, 2 * l, 2):
+        v *= i
+    return v
+
+
+def test_double_factorial_tables_correctly_rounded():
+    assert C["poly_orders"] == 33 and len(C["dfact"]) == 33 and len(C["inv_dfact"]) == 33
+    for l in range(33):
+        d = odd_dfact(l)
+        assert abs(Fraction(C["dfact"][l]) - d) <= Fraction(math.ulp(C["dfact"][l])) / 2, l
+        inv = Fraction(1, d)
+        assert abs(Fraction(C["inv_dfact"][l]) - inv) <= Fraction(math.ulp(C["inv_dfact"][l])) / 2, l
+
+
+def rnd(q):
+    """The double nearest the rational q."""
+    return float(q)
+
+
+def sweep_a(x, w, S, e, CH=4, mistake=None):
+    """Region A as the kernel runs it: table entries (w_s D_s/D_k, D_k/D_s),
+    (w_0/D_k, 0) at s = 0, zeros below, swept upwards in whole chunks from
+    below, z first, then sum = z S + v e."""
+    k = len(w) - 1
+    D, ID = C["dfact"], C["inv_dfact"]
+    dk, idk = D[k], ID[k]
+    ent = {}
+    for s in range(k + 1):
+        a = rnd(Fraction(w[s]) * Fraction(rnd(Fraction(D[s]) * Fraction(idk))))
+        b = rnd(Fraction(ID[s]) * Fraction(dk)) if s >= 1 else 0.0
+        if mistake == "no_scale":
+            a = rnd(Fraction(w[s]) * Fraction(D[s]))
+        ent[s] = (a, b)
+    steps = (k + CH) & ~(CH - 1)
+    two_x = x + x
+    z = v = 0.0
+    for s in range(k + 1 - steps, k + 1):
+        a, b = ent.get(s, (0.0, 0.0))
+        if mistake == "new_z":
+            z = fma(two_x, z, a)
+            v = fma(z, b, v)
+        else:
+            z, v = fma(two_x, z, a), fma(z, b, v)
+    return fma(z, S, rnd(Fraction(v) * Fraction(e)))
+
+
+def sweep_b(x, w, S, e, CH=4, mistake=None):
+    """Region B as the kernel runs it: table entries l = 1..top,
+    (w_{l-1} D_{l-1}, -1/D_l) for l <= k, (w_k D_k, 0) at l = k+1, zeros
+    above, swept downwards in whole chunks from above, z first, then
+    sum = z S + (g v) e with g = 1/(2x)."""
+    k = len(w) - 1
+    D, ID = C["dfact"], C["inv_dfact"]
+    top = (k + CH) & ~(CH - 1)
+    g = rnd(Fraction(1) / (2 * Fraction(x)))
+    z = v = 0.0
+    for l in range(top, 0, -1):
+        a = rnd(Fraction(w[l - 1]) * Fraction(D[l - 1])) if l - 1 <= k else 0.0
+        b = -ID[l] if l <= k else 0.0
+        if mistake == "sign":
+            b = -b
+        if mistake == "shift":
+            a = rnd(Fraction(w[l]) * Fraction(D[l])) if 1 <= l <= k else 0.0
+        z, v = fma(g, z, a), fma(z, b, v)
+    return fma(z, S, rnd(Fraction(rnd(Fraction(g) * Fraction(v))) * Fraction(e)))
+
+
+def exact_F(x, K):
+    """F_0..F_K(x) from mpmath's incomplete gamma (50 digits)."""
+    mp.mp.dps = 50
+    xm = mp.mpf(x)
+    return [mp.gammainc(l + mp.mpf(1) / 2, 0, xm) / (2 * xm ** (l + mp.mpf(1) / 2)) for l in range(K + 1)]
+
+
+def sweep_cases():
+    rng = np.random.default_rng(2024)
+    cases = []
+    for K in range(33):
+        cases.append((K, float(rng.uniform(0.05, X0)), "A"))
+        cases.append((K, float(rng.uniform(X0, X1)), "B"))
+    cases += [(32, float(np.nextafter(X0, 0)), "A"), (32, X0, "B"), (32, X1, "B"), (5, 1e-3, "A")]
+    return cases
+
+
+def check_sweeps(mistake=None, CH=4):
+    rng = np.random.default_rng(7)
+    u = 2.0 ** -53
+    for K, x, region in sweep_cases():
+        w = [float(v) for v in rng.standard_normal(K + 1)]
+        F = exact_F(x, K)
+        exact = sum(mp.mpf(wl) * Fl for wl, Fl in zip(w, F))
+        e = mp.exp(-mp.mpf(x))
+        if region == "A":
+            got = sweep_a(x, w, float(F[K]), float(e), CH, mistake)
+            scale = sum(abs(wl) * Fl for wl, Fl in zip(w, F))
+        else:
+            got = sweep_b(x, w, float(F[0]), float(e), CH, mistake)
+            scale = F[0] * sum(abs(wl) for wl in w)
+        bound = 4 * (K + 2) * u * scale
+        assert abs(mp.mpf(got) - exact) <= bound, (K, x, region, float(abs(mp.mpf(got) - exact) / scale))
+
+
+@pytest.mark.parametrize("CH", [4, 8])
+def test_weight_sweeps_reproduce_the_weighted_sum(CH):
+    check_sweeps(CH=CH)
+
+
+@pytest.mark.parametrize("mistake", ["no_scale", "new_z", "sign", "shift"])
+def test_weight_sweep_check_detects_planted_mistakes(mistake):
+    with pytest.raises(AssertionError):
+        check_sweeps(mistake=mistake)
