@@ -71,38 +71,6 @@ __device__ __forceinline__ double exp_neg(double x) {
   return __builtin_amdgcn_ldexp(p, -int(nd));
 }
 
-// The address of a constant table, hidden from the optimiser: reads through
-// it stay scalar loads instead of being folded back into literals (two scalar
-// moves each) from the table's known initializer.
-#define BOYS_CONST_AS __attribute__((address_space(4)))
-template <class P>
-__device__ __forceinline__ const BOYS_CONST_AS P *opaque(const P *p) {
-  auto q = (const BOYS_CONST_AS P *)(p);
-  asm("" : "+s"(q));
-  return q;
-}
-
-// The same routine with its constants read from constant memory by scalar
-// loads (a few wide loads per evaluation instead of two scalar moves per
-// literal) for the batched consumer, whose issue slots the moves compete for.
-struct ExpConsts {
-  double inv_ln2, ln2_hi, ln2_lo, pad;
-  double taylor[kExpDegree + 1];
-};
-static __constant__ const ExpConsts kExpConsts = {BOYS_EXP_INV_LN2, BOYS_EXP_LN2_HI, BOYS_EXP_LN2_LO,
-                                                  0.0, BOYS_EXP_TAYLOR_INIT};
-
-__device__ __forceinline__ double exp_neg_loaded(double x) {
-  const BOYS_CONST_AS ExpConsts &c = *opaque(&kExpConsts);
-  const double nd = __builtin_rint(x * c.inv_ln2);
-  double r = __builtin_fma(nd, c.ln2_hi, -x);
-  r = __builtin_fma(nd, c.ln2_lo, r);
-  double p = add_uniform(r * c.taylor[kExpDegree], c.taylor[kExpDegree - 1]);
-#pragma unroll
-  for (int j = kExpDegree - 2; j >= 0; --j) p = fma_uniform_addend(p, r, c.taylor[j]);
-  return __builtin_amdgcn_ldexp(p, -int(nd));
-}
-
 // 1/x for finite x in the normal range: the hardware reciprocal refined by
 // two Newton steps (within about one ulp).
 __device__ __forceinline__ double recip(double x) {
@@ -237,8 +205,8 @@ __device__ __forceinline__ double rational_loaded(double x, const double *P, con
 }
 
 // As rational_loaded, with div_positive for the quotient.
-template <int NP, int NQ, class Ptr>
-__device__ __forceinline__ double rational_loaded_pos(double x, Ptr P, Ptr Q) {
+template <int NP, int NQ>
+__device__ __forceinline__ double rational_loaded_pos(double x, const double *P, const double *Q) {
   double p = P[NP];
 #pragma unroll
   for (int i = NP - 1; i >= 0; --i) p = fma_uniform_addend(p, x, P[i]);
@@ -269,29 +237,17 @@ __device__ __forceinline__ double rational_a_rt_pos(double x, int k) {
   return rational_loaded_pos<R::pad_n, R::hi_m>(x, P, Q);
 }
 
-// r_B of a table set, its coefficients read from constant memory with scalar
-// loads (a few wide loads instead of two scalar moves per literal).
+// r_B of a table set with div_positive for the quotient (literal
+// coefficients, SGPR addends, as rational_b_t).
 template <class T>
-struct RbRow {
-  double p[T::rb_n + 1];
-  double q[T::rb_m + 1];
-};
-template <class T>
-constexpr RbRow<T> make_rb_row() {
-  RbRow<T> r{};
-  for (int i = 0; i <= T::rb_n; ++i) r.p[i] = T::rb_p[i];
-  for (int i = 0; i <= T::rb_m; ++i) r.q[i] = T::rb_q[i];
-  return r;
-}
-static __constant__ const RbRow<PaperTables> kRbRow = make_rb_row<PaperTables>();
-static __constant__ const RbRow<ScreenTables> kRbRowScreen = make_rb_row<ScreenTables>();
-
-template <class T>
-__device__ __forceinline__ double rational_b_pos(double x) {
-  const BOYS_CONST_AS RbRow<T> *r;
-  if constexpr (std::is_same_v<T, ScreenTables>) r = opaque(&kRbRowScreen);
-  else r = opaque(&kRbRow);
-  return rational_loaded_pos<T::rb_n, T::rb_m>(x, r->p, r->q);
+__device__ __forceinline__ double rational_b_lit_pos(double x) {
+  double p = T::rb_p[T::rb_n];
+#pragma unroll
+  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::rb_p[i]);
+  double q = x + T::rb_q[T::rb_m - 1];
+#pragma unroll
+  for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::rb_q[i]);
+  return div_positive(p, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +320,7 @@ __device__ __forceinline__ double fma_step(double h, double t, double c) {
 // for 1 <= s <= k, (w_0/(2k-1)!!, 0) for s = 0, zeros for s < 0.
 template <int CH, class T = PaperTables>
 __device__ __forceinline__ double wsum_sweep_a(double x, int k, const wpair *ta) {
-  const double e = exp_neg_loaded(x);
+  const double e = exp_neg(x);
   const double S = rational_a_rt_pos<T>(x, k);
   const double two_x = x + x;
   const int steps = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
@@ -388,9 +344,9 @@ __device__ __forceinline__ double wsum_sweep_a(double x, int k, const wpair *ta)
 // (w_k (2k-1)!!, 0) for l = k+1, zeros above.
 template <int CH, class T = PaperTables>
 __device__ __forceinline__ double wsum_sweep_b(double x, int k, const wpair *tb) {
-  const double e = exp_neg_loaded(x);
+  const double e = exp_neg(x);
   const double g = 0.5 * recip(x);
-  const double S = rational_b_pos<T>(x);
+  const double S = rational_b_lit_pos<T>(x);
   const int top = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
   double z = 0.0, v = 0.0;
   for (int l0 = top; l0 > 0; l0 -= CH) {
