@@ -54,16 +54,36 @@ KERNEL_SOURCES = ["paper_2512_10059_amd/csrc/boys_eval_f64.hip",
                   "paper_2512_10059_amd/build.py"]
 
 
+FUSED_KT_SUMMARY = os.path.join(ROOT, "profiles", "weighted_sum_8192_batches_kernel_stats.md")
+FUSED_PMC_SUMMARY = os.path.join(ROOT, "profiles", "weighted_sum_8192_batches_pmc.md")
+FUSED_SOURCES = ["paper_2512_10059_amd/csrc/boys_weighted_sum.hip",
+                 "paper_2512_10059_amd/csrc/boys_device_f64_batched.hpp",
+                 "paper_2512_10059_amd/csrc/boys_device_f64.hpp",
+                 "paper_2512_10059_amd/csrc/boys_coeffs_f64.h",
+                 "paper_2512_10059_amd/csrc/boys_coeffs_f64_screen.h",
+                 "paper_2512_10059_amd/csrc/boys_consumer_tables.h",
+                 "paper_2512_10059_amd/build.py"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def summary_values(path, sources):
+    """The '- key: value' lines of a committed profile summary, or None when
+    it is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    vals = dict(re.findall(r"^- (\w+): (\S+)\s*$", open(path).read(), re.M))
+    return vals if vals.get("source_sha256") == kernel_source_hash(sources) else None
 
 
 def pmc_traffic_bytes():
@@ -226,12 +246,33 @@ def leg_fused(torch, boys, workloads, steps, warmup, dev):
     flops = float(algorithmic_flops(bt.x, kk, f64_region_a_degrees()))
     nbytes = bt.x.size * 16 + bt.w.size * 8 + bt.batch_n.size * 24
     log(f"fused: {ms:.3f} ms, config {name}; screening tables {ms_screen:.3f} ms")
-    return {"nbatch": int(bt.batch_n.size), "arguments": int(bt.x.size), "values": values,
-            "ms": ms, "config": name, "tune_ms": tune_ms, "ms_screen_1e-10": ms_screen,
-            "values_per_s": values / (ms * 1e-3),
-            "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
-            "fp64_peak_frac_algorithmic": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-            "gbs": nbytes / (ms * 1e6)}
+    res = {"nbatch": int(bt.batch_n.size), "arguments": int(bt.x.size), "values": values,
+           "ms": ms, "config": name, "tune_ms": tune_ms, "ms_screen_1e-10": ms_screen,
+           "values_per_s": values / (ms * 1e-3),
+           "algorithmic_flop_per_call": flops,
+           "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
+           "fp64_peak_frac_algorithmic": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+           "gbs": nbytes / (ms * 1e6)}
+    # The persistent kernel alone (a call is the scan, this kernel and the
+    # graph's launch gaps), from the committed rocprofv3 summaries when they
+    # were taken on the current sources: its median duration, the
+    # algorithmic and the issued FP64 rates against the 78.6 TFLOP/s peak.
+    kt = summary_values(FUSED_KT_SUMMARY, FUSED_SOURCES)
+    pmc = summary_values(FUSED_PMC_SUMMARY, FUSED_SOURCES)
+    kernel = None
+    if kt is not None:
+        us = float(kt["main_kernel_median_us"])
+        kernel = {"name": kt.get("main_kernel"), "median_us": us,
+                  "algorithmic_tflops": flops / (us * 1e-6) / 1e12,
+                  "fp64_peak_frac_algorithmic": flops / (us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS,
+                  "issued_fp64_flop": None, "fp64_peak_frac_issued": None,
+                  "gbs": nbytes / (us * 1e3)}
+        if pmc is not None:
+            issued = float(pmc["issued_fp64_flop_per_dispatch"])
+            kernel["issued_fp64_flop"] = issued
+            kernel["fp64_peak_frac_issued"] = issued / (us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS
+    res["kernel_from_profiles"] = kernel
+    return res
 
 
 def leg_backward(torch, boys, workloads, steps, warmup, dev):

@@ -208,11 +208,21 @@ BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
 
 /*
  * Times every configuration of the persistent kernel (tile length, region
- * binning on or off, grid of 1 to 3 rounds of resident workgroups) on these
- * arguments (each run writes out), keeps the fastest for later
- * boys_weighted_sum calls on this device, and reports it.  Synchronises
- * `stream`.  best_config (may be NULL) receives the configuration index,
- * best_ms (may be NULL) its time in milliseconds.
+ * binning on or off, sweep chunk, grid of 2 to 4 rounds of resident
+ * workgroups, equal or tapered per-wave shares) on these arguments (each run
+ * writes out), keeps the fastest for later boys_weighted_sum calls on this
+ * device, and reports it.  Synchronises `stream`.  best_config (may be NULL)
+ * receives the configuration index, best_ms (may be NULL) its time in
+ * milliseconds.
+ *
+ * If the environment variable BOYS_TUNE_CACHE names a file, the result is
+ * appended to it as "weighted_sum <arch> <set> <bucket> <name>" (device
+ * architecture, table set, floor(log2 nbatch), configuration name), and the
+ * first boys_weighted_sum(_tol) call on a device that has not chosen a
+ * configuration takes the last matching entry; without a match (no
+ * variable, no file, another device or build, malformed lines) it takes the
+ * default.  boys_weighted_sum_noalloc reads no file: it uses the configuration
+ * already chosen on the device, else the default.
  */
 BOYS_API int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
                            const int32_t *batch_kmax, const double *w, const int64_t *w_off,

@@ -576,6 +576,7 @@ struct DeviceState {
   GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
   int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
+  char arch[32] = {};  // the device's architecture name (up to the first ':')
   int resident[2][kNumConfigs] = {};  // workgroups per CU, 0: not queried yet
   void *scratch_ptr = nullptr;         // this device's copy of `scratch`
   bool has_graphs() const {
@@ -653,29 +654,48 @@ void drop_graphs(DeviceState &s) {
   s.retired_graphs.clear();
 }
 
-// Configuration from the tuning cache file named by BOYS_TUNE_CACHE (lines
-// "weighted_sum <log2 nbatch> <config>"), else the default.
-int cached_config(int32_t nbatch) {
+// The tuning cache: the file named by BOYS_TUNE_CACHE holds lines
+//     weighted_sum <arch> <table set> <bucket> <configuration name>
+// (bucket = floor(log2 nbatch)).  A lookup takes the last line whose device
+// architecture, table set and bucket match this call and whose name is one of
+// this build's configurations; anything else (no variable, no file, other
+// devices or builds, malformed lines) leaves the default.  Names rather than
+// indices keep entries valid when the configuration table changes.
+int nbatch_bucket(int32_t nbatch) { return nbatch > 0 ? int(std::log2(double(nbatch))) : 0; }
+
+int config_by_name(const char *name) {
+  for (int c = 0; c < kNumConfigs; ++c)
+    if (std::strcmp(kConfigs[c].name, name) == 0) return c;
+  return -1;
+}
+
+int cached_config(const char *arch, int32_t nbatch, int set) {
   const char *path = std::getenv("BOYS_TUNE_CACHE");
   int best = kDefaultConfig;
-  if (!path) return best;
+  if (!path || !arch[0]) return best;
   FILE *f = std::fopen(path, "r");
   if (!f) return best;
-  const int bucket = nbatch > 0 ? int(std::log2(double(nbatch))) : 0;
-  char name[64];
-  int bk = 0, cfg = 0;
-  while (std::fscanf(f, "%63s %d %d", name, &bk, &cfg) == 3)
-    if (std::strcmp(name, "weighted_sum") == 0 && bk == bucket && cfg >= 0 && cfg < kNumConfigs)
-      best = cfg;
+  const int bucket = nbatch_bucket(nbatch);
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    char tag[32], a[32], name[96];
+    int st = -1, bk = -1;
+    char extra;
+    if (std::sscanf(line, "%31s %31s %d %d %95s %c", tag, a, &st, &bk, name, &extra) != 5) continue;
+    if (std::strcmp(tag, "weighted_sum") != 0 || std::strcmp(a, arch) != 0 || st != set || bk != bucket)
+      continue;
+    const int c = config_by_name(name);
+    if (c >= 0) best = c;
+  }
   std::fclose(f);
   return best;
 }
 
-void store_config(int32_t nbatch, int cfg) {
+void store_config(const char *arch, int32_t nbatch, int set, int cfg) {
   const char *path = std::getenv("BOYS_TUNE_CACHE");
-  if (!path) return;
+  if (!path || !arch[0]) return;
   if (FILE *f = std::fopen(path, "a")) {
-    std::fprintf(f, "weighted_sum %d %d\n", nbatch > 0 ? int(std::log2(double(nbatch))) : 0, cfg);
+    std::fprintf(f, "weighted_sum %s %d %d %s\n", arch, set, nbatch_bucket(nbatch), kConfigs[cfg].name);
     std::fclose(f);
   }
 }
@@ -815,6 +835,12 @@ int device_state(DeviceState **out) {
   if (s.cus == 0) {
     int cus = 0;
     BOYS_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipDeviceProp_t prop;
+    BOYS_TRY_HIP(hipGetDeviceProperties(&prop, dev));
+    size_t i = 0;
+    for (; i + 1 < sizeof(s.arch) && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+      s.arch[i] = prop.gcnArchName[i];
+    s.arch[i] = 0;
     s.cus = cus > 0 ? cus : 1;
   }
   *out = &s;
@@ -842,7 +868,7 @@ int weighted_sum_with_set(const Call &c, int set, hipStream_t stream) {
   DeviceState *s = nullptr;
   if (int st = device_state(&s)) return st;
   std::lock_guard<std::mutex> lock(s->mu);
-  if (s->config < 0) s->config = cached_config(c.nbatch);
+  if (s->config < 0) s->config = cached_config(s->arch, c.nbatch, set);
   return launch(*s, c, s->config, set, stream);
 }
 
@@ -974,7 +1000,7 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   (void)hipEventDestroy(e1);
   if (st != BOYS_OK) return st;
   s->config = best;
-  store_config(nbatch, best);
+  store_config(s->arch, nbatch, 0, best);
   if ((st = launch(*s, c, best, 0, stream))) return st;  // leaves the graph of the winner cached
   if (best_config) *best_config = best;
   if (best_ms) *best_ms = best_t;

@@ -189,6 +189,51 @@ def test_tuner_picks_a_valid_config():
     boys.weighted_sum_set_config(-1)
 
 
+def test_tuning_cache_file(tmp_path, monkeypatch):
+    """BOYS_TUNE_CACHE: a missing file, garbage, another architecture, another
+    table set or bucket, and an unknown configuration name all leave the
+    default; a matching line selects its configuration, and the last
+    matching line wins."""
+    bt = small_batches(seed=11)
+    args = to_dev(bt)
+    nb = bt.batch_off.size
+    bucket = int(np.floor(np.log2(nb)))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    names = [boys.weighted_sum_config_name(c) for c in range(boys.weighted_sum_num_configs())]
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BOYS_TUNE_CACHE", str(path))
+
+    def chosen(text):
+        if text is None:
+            if path.exists():
+                path.unlink()
+        else:
+            path.write_bytes(text if isinstance(text, bytes) else text.encode())
+        boys.weighted_sum_set_config(-1)  # the next call consults the cache
+        out = boys.boys_weighted_sum(*args).cpu().numpy()
+        check(bt, out)
+        return boys.weighted_sum_get_config()
+
+    try:
+        default = chosen(None)
+        other = (default + 1) % len(names)
+        assert chosen(b"\x00\xff garbage\n\nweighted_sum\n1 2 3\n") == default
+        assert chosen(f"weighted_sum gfx942 0 {bucket} {names[other]}\n") == default
+        assert chosen(f"weighted_sum {arch} 1 {bucket} {names[other]}\n") == default
+        assert chosen(f"weighted_sum {arch} 0 {bucket + 1} {names[other]}\n") == default
+        assert chosen(f"weighted_sum {arch} 0 {bucket} no-such-config\n") == default
+        assert chosen(f"weighted_sum {arch} 0 {bucket} {names[other]}\n") == other
+        assert chosen(f"weighted_sum {arch} 0 {bucket} {names[other]}\n"
+                      f"weighted_sum {arch} 0 {bucket} {names[default]}\n") == default
+        # The tuner appends its choice under the same key.
+        path.unlink()
+        cfg, ms, name = boys.boys_tune_weighted_sum(*args)
+        lines = path.read_text().split("\n")
+        assert lines[0].split() == ["weighted_sum", arch, "0", str(bucket), name]
+    finally:
+        boys.weighted_sum_set_config(-1)
+
+
 def test_invalid_arguments_raise():
     bt = small_batches(seed=4)
     args = list(to_dev(bt))
