@@ -21,11 +21,13 @@ Beside the headline the same JSON line carries:
                 at kmax=30), the paper's
                 own N^2 benchmark (n = 2^19, k = 12) beside its A100 time, and
                 the screening table set (eps_tol = 1e-10) on the write-out
-                and pair-sum workloads, and the write-out at kmax = 40 (the
-                high-order tables).
+                and pair-sum workloads, the write-out at kmax = 40 (the
+                high-order tables), and the variants of the 5e-14 tables
+                (per-kmax regions, centre-of-anti-diagonal degrees) on the
+                fused, write-out and pair-sum work.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
-       [--only writeout,mixed,fp32,fused,backward,pairsum,screen,high]
+       [--only writeout,mixed,fp32,fused,backward,pairsum,screen,high,variants]
        [--no-cpu-baseline] [--copy-probe]
 """
 from __future__ import annotations
@@ -50,6 +52,8 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "eval_f64_writeout_k32_n2e26_pmc.md
 KERNEL_SOURCES = ["paper_2512_10059_amd/csrc/boys_eval_f64.hip",
                   "paper_2512_10059_amd/csrc/boys_device_f64.hpp",
                   "paper_2512_10059_amd/csrc/boys_coeffs_f64.h",
+                  "paper_2512_10059_amd/csrc/boys_coeffs_f64_perk.h",
+                  "paper_2512_10059_amd/csrc/boys_coeffs_f64_centre.h",
                   "paper_2512_10059_amd/csrc/boys_common.hpp",
                   "paper_2512_10059_amd/build.py"]
 
@@ -61,6 +65,8 @@ FUSED_SOURCES = ["paper_2512_10059_amd/csrc/boys_weighted_sum.hip",
                  "paper_2512_10059_amd/csrc/boys_device_f64.hpp",
                  "paper_2512_10059_amd/csrc/boys_coeffs_f64.h",
                  "paper_2512_10059_amd/csrc/boys_coeffs_f64_screen.h",
+                 "paper_2512_10059_amd/csrc/boys_coeffs_f64_perk.h",
+                 "paper_2512_10059_amd/csrc/boys_coeffs_f64_centre.h",
                  "paper_2512_10059_amd/csrc/boys_consumer_tables.h",
                  "paper_2512_10059_amd/build.py"]
 
@@ -394,6 +400,63 @@ def leg_high(torch, boys, workloads, steps, warmup, dev, wo=None):
     return res
 
 
+def leg_variants(torch, boys, workloads, steps, warmup, dev, wo=None):
+    """The variants of the 5e-14 tables (boys_set_tables: the paper's, the
+    per-kmax regions, the centre-of-anti-diagonal refit) on the same work:
+    the batched consumer on the 8192-batch workload (the configuration
+    already chosen), the write-out of the headline arguments at kmax = 4, 12
+    and 24, and the pair sums at n = 2^17 for k = 5 (where the centre pick
+    changes the degrees of r_{A,5} from (4, 13) to (8, 9)) and k = 12.
+    The variants are timed in interleaved rounds (each round times every
+    variant once, a few calls each) and each reports the median of its
+    rounds: timed one after another, the first variant of a block ran up to
+    10% slower or faster than the same kernel later in the run."""
+    names = {"paper": boys.TABLES_PAPER, "per_kmax": boys.TABLES_PER_KMAX,
+             "centre": boys.TABLES_CENTRE}
+    rounds = 5
+
+    def interleaved(call, calls_per_round):
+        times = {name: [] for name in names}
+        for name, v in names.items():  # warm-up (graphs, workspaces)
+            with boys.table_variant(v):
+                for _ in range(max(1, warmup)):
+                    call()
+        for _ in range(rounds):
+            for name, v in names.items():
+                with boys.table_variant(v):
+                    with Timer(torch) as tm:
+                        for _ in range(calls_per_round):
+                            call()
+                times[name].append(tm.ms / calls_per_round)
+        return {name: float(np.median(t)) for name, t in times.items()}
+
+    res = {"rounds": rounds}
+    bt = workloads.batched_workload()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    args = (t(bt.x), t(bt.batch_off), t(bt.batch_n), t(bt.batch_kmax), t(bt.w), t(bt.w_off))
+    out = torch.zeros_like(args[0])
+    res["fused_config"] = boys.weighted_sum_config_name(boys.weighted_sum_get_config())
+    res["fused_ms"] = interleaved(lambda: boys.boys_weighted_sum(*args, out=out), max(1, steps // 4))
+    del args, out
+    n = workloads.N_WRITEOUT
+    x = wo["x"] if wo else torch.from_numpy(workloads.gaussian_pair_arguments(n)).to(dev)
+    res["writeout_ms"] = {}
+    for kmax in (4, 12, 24):
+        o = torch.empty((n, kmax + 1), dtype=torch.float64, device=dev)
+        res["writeout_ms"][f"kmax{kmax}"] = interleaved(lambda: boys.boys_eval_f64(x, kmax, out=o),
+                                                        max(1, steps // 4))
+        del o
+    torch.cuda.empty_cache()
+    res["pairsum_ms"] = {}
+    for kmax in (5, 12):
+        xh, yh, c = workloads.pair_workload(n=1 << 17, kmax=kmax)
+        xp, yp = torch.from_numpy(xh).to(dev), torch.from_numpy(yh).to(dev)
+        z = torch.empty_like(xp)
+        res["pairsum_ms"][f"n2e17_k{kmax}"] = interleaved(lambda: boys.boys_pairsum(xp, yp, c, out=z), 1)
+    log(f"variants: fused {res['fused_ms']}; write-out {res['writeout_ms']}; pairs {res['pairsum_ms']}")
+    return res
+
+
 def cpu_model() -> str:
     """The host CPU's model name (first processor in /proc/cpuinfo)."""
     try:
@@ -475,7 +538,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="writeout,mixed,fp32,fused,backward,pairsum,screen,high")
+    ap.add_argument("--only", default="writeout,mixed,fp32,fused,backward,pairsum,screen,high,variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -540,6 +603,11 @@ def main():
             extra["high"] = leg_high(torch, boys, workloads, args.steps, args.warmup, dev, wo)
         except Exception as e:
             extra["high"] = {"error": str(e)}
+    if "variants" in legs:
+        try:
+            extra["variants"] = leg_variants(torch, boys, workloads, args.steps, args.warmup, dev, wo)
+        except Exception as e:
+            extra["variants"] = {"error": str(e)}
     if wo is None:  # profiling runs of single legs
         print(json.dumps({"legs": extra}))
         return

@@ -84,6 +84,40 @@ enum {
 #define BOYS_F64_BACKWARD_KMAX_LIMIT 39
 #define BOYS_F32_KMAX_LIMIT 16
 
+/*
+ * Which tables serve the paper's accuracy (5e-14) at orders 0..32, for every
+ * call with tol < 1e-10 (all entry points without _tol, and the _tol ones
+ * below 1e-10) except boys_backward(_tol), which always takes the paper's:
+ *
+ *   BOYS_TABLES_PAPER     the paper's appendix: x0 = 11.899848152108484 and
+ *                         x1 = 28.98933773882074, the regions of kmax = 32,
+ *                         for every kmax (the default).
+ *   BOYS_TABLES_PER_KMAX  the regions of the call's own kmax (Sec. II C: x0
+ *                         and x1 depend on the highest order evaluated):
+ *                         x0(K) = max{1, (prod_{n<K} (n+1/2))^(1/K)}, x1(K)
+ *                         the root of the asymptote-error equation at 5e-14
+ *                         for F_K (rounded up to a double), and r_B on
+ *                         [x0(K), x1(K)] and r_{A,K} on [0, x0(K)] computed
+ *                         with the library's Remez tool and the Walsh-table
+ *                         degree choice; kmax = 32 is the paper's set.  The
+ *                         batched consumer applies each batch's own kmax.
+ *   BOYS_TABLES_CENTRE    the paper's x0 and x1, with r_B and every r_{A,k}
+ *                         refitted at the Walsh-table entry nearest the
+ *                         centre of the first feasible anti-diagonal
+ *                         (n close to m; Sec. II D's alternative choice).
+ *
+ * Every variant keeps |error| <= 5e-14.  The setting is process-wide (all
+ * devices and threads) and applies to calls made after it returns; work
+ * already enqueued is not affected.  boys_set_tables returns BOYS_EINVAL for
+ * an unknown variant (and changes nothing); boys_get_tables returns the
+ * current one.
+ */
+#define BOYS_TABLES_PAPER 0
+#define BOYS_TABLES_PER_KMAX 1
+#define BOYS_TABLES_CENTRE 2
+BOYS_API int boys_set_tables(int variant);
+BOYS_API int boys_get_tables(void);
+
 /* Text for a status code (static storage, never NULL). */
 BOYS_API const char *boys_strerror(int status);
 
@@ -96,7 +130,8 @@ BOYS_API int boys_last_hip_error(void);
  *   x      [n] FP64 arguments.
  *   out    row-major n x ld_out FP64: out[i*ld_out + k] = F_k(x[i]) for
  *          k = 0..kmax; columns kmax+1..ld_out-1 are left untouched.
- *   kmax   0 <= kmax <= 40.  Up to 32 the paper's tables (r_{A,kmax} is the
+ *   kmax   0 <= kmax <= 40.  Up to 32 the paper's tables, or the variant
+ *          chosen with boys_set_tables (r_{A,kmax} is the
  *          region-A approximant used); 33..40 a table set built the same way
  *          for kmax = 40 at the same 5e-14 (x0 = 14.842842360917231, x1 and
  *          every rational from the library's Remez tool), whose guarantee
@@ -117,7 +152,8 @@ BOYS_API int boys_eval_f64(const double *x, int64_t n, int kmax, double *out, in
  *                  1e-10, root rounded up), r_B and r_{A,k} computed with the
  *                  library's Remez tool (Walsh-table degree choice, lower
  *                  degrees than the paper's); |error| <= 1e-10.
- *   tol >= 5e-14   the paper's tables (identical to boys_eval_f64).
+ *   tol >= 5e-14   the paper's tables or the boys_set_tables variant
+ *                  (identical to boys_eval_f64).
  * Orders 33..40 exist only at 5e-14 (the high-order tables) and take them
  * for any tol >= 5e-14.  Arguments and layout as boys_eval_f64.  Errors: as
  * boys_eval_f64, and BOYS_EINVAL for tol < 5e-14 or NaN.
@@ -175,8 +211,8 @@ BOYS_API int boys_weighted_sum(const double *x, const int64_t *batch_off, const 
  * boys_weighted_sum for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation.  Same arguments, same kernels and the same result, bit for bit,
- * as boys_weighted_sum (the paper's tables, the configuration chosen for
- * boys_weighted_sum).  The scan's prefix arrays live in a fixed device array
+ * as boys_weighted_sum (the 5e-14 tables of the variant set by
+ * boys_set_tables, the configuration chosen for boys_weighted_sum).  The scan's prefix arrays live in a fixed device array
  * of 2 (BOYS_NOALLOC_MAX_BATCHES + 1) int64 (1 MiB), one copy per device,
  * held until the process ends; the two kernels are launched directly on
  * `stream` (no cached graph), so the call enqueues only kernel launches and
@@ -196,9 +232,10 @@ BOYS_API int boys_weighted_sum_noalloc(const double *x, const int64_t *batch_off
 /*
  * boys_weighted_sum with the table set chosen by tol as in boys_eval_f64_tol:
  * tol >= 1e-10 takes the screening set (per argument |error| <= 1e-10
- * sum_l |w_l| plus rounding), 5e-14 <= tol < 1e-10 the paper's tables (the
- * same result as boys_weighted_sum, bit for bit).  The configuration chosen
- * by boys_tune_weighted_sum serves both sets.  Errors: as boys_weighted_sum,
+ * sum_l |w_l| plus rounding), 5e-14 <= tol < 1e-10 the 5e-14 tables of the
+ * variant set by boys_set_tables (the same result as boys_weighted_sum, bit
+ * for bit).  The configuration chosen by boys_tune_weighted_sum serves every
+ * set.  Errors: as boys_weighted_sum,
  * and BOYS_EINVAL for tol < 5e-14 or NaN.
  */
 BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
@@ -210,14 +247,16 @@ BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
  * Times every configuration of the persistent kernel (tile length, region
  * binning on or off, sweep chunk, grid of 2 to 4 rounds of resident
  * workgroups, equal or tapered per-wave shares) on these arguments (each run
- * writes out), keeps the fastest for later boys_weighted_sum calls on this
- * device, and reports it.  Synchronises `stream`.  best_config (may be NULL)
+ * writes out) with the 5e-14 tables of the current boys_set_tables variant,
+ * keeps the fastest for later boys_weighted_sum calls on this device, and
+ * reports it.  Synchronises `stream`.  best_config (may be NULL)
  * receives the configuration index, best_ms (may be NULL) its time in
  * milliseconds.
  *
  * If the environment variable BOYS_TUNE_CACHE names a file, the result is
  * appended to it as "weighted_sum <arch> <set> <bucket> <name>" (device
- * architecture, table set, floor(log2 nbatch), configuration name), and the
+ * architecture, table set: 0 the paper's, 2 per-kmax, 3 centre, then
+ * floor(log2 nbatch) and the configuration name), and the
  * first boys_weighted_sum(_tol) call on a device that has not chosen a
  * configuration takes the last matching entry; without a match (no
  * variable, no file, another device or build, malformed lines) it takes the
@@ -273,7 +312,8 @@ BOYS_API int boys_backward_tol(const double *x, const double *grad_f, int64_t n,
  *
  *   x, y, z  device arrays [n] (FP64); z must not overlap x or y.
  *   c        HOST array of kmax+1 FP64 weights, read during the call.
- *   n        0 <= n <= 2^31 - 1.   kmax 0..40 (orders above 32 take the
+ *   n        0 <= n <= 2^31 - 1.   kmax 0..40 (up to 32 the paper's tables
+ *            or the boys_set_tables variant; orders above 32 take the
  *            high-order tables, as boys_eval_f64).
  * Each z[i] is summed over j in chunks of 512 terms (chunk sums added in
  * order), so its rounding is about (512 + n/512) ulps of sum_j |y_j w_ij|
@@ -291,7 +331,8 @@ BOYS_API int boys_pairsum(const double *x, const double *y, int64_t n, const dou
 /*
  * boys_pairsum with the table set chosen by tol as in boys_eval_f64_tol
  * (tol >= 1e-10: screening set, per-term bound 1e-10 sum_l |c_l|; tol >=
- * 5e-14: the paper's; orders above 32 take the high-order tables for any
+ * 5e-14: the paper's or the boys_set_tables variant; orders above 32 take
+ * the high-order tables for any
  * tol >= 5e-14).  Errors: as boys_pairsum, and BOYS_EINVAL for
  * tol < 5e-14 or NaN.
  */

@@ -15,7 +15,8 @@ _BINDING_NAMES = {
     "boys_weighted_sum_noalloc",
     "boys_tune_weighted_sum", "boys_backward", "boys_pairsum", "weighted_sum_config_name",
     "weighted_sum_num_configs", "weighted_sum_get_config", "weighted_sum_set_config",
-    "finalize", "lib", "library_path", "F64_KMAX", "F64_KMAX_EVAL", "F64_KMAX_BACKWARD", "F32_KMAX",
+    "finalize", "lib", "library_path", "set_tables", "get_tables", "table_variant", "TABLES_PAPER",
+    "TABLES_PER_KMAX", "TABLES_CENTRE", "F64_KMAX", "F64_KMAX_EVAL", "F64_KMAX_BACKWARD", "F32_KMAX",
 }
 
 

@@ -46,7 +46,14 @@ _SIGNATURES = {
     "boys_pairsum": ([_P, _P, _I64, _P, _INT, _P, _P], _INT),
     "boys_pairsum_tol": ([_P, _P, _I64, _P, _INT, ctypes.c_double, _P, _P], _INT),
     "boys_finalize": ([], None),
+    "boys_set_tables": ([_INT], _INT),
+    "boys_get_tables": ([], _INT),
 }
+
+# Variants of the 5e-14 tables for orders up to 32 (boys_set_tables).
+TABLES_PAPER = 0
+TABLES_PER_KMAX = 1
+TABLES_CENTRE = 2
 
 
 class BoysError(RuntimeError):
@@ -171,8 +178,8 @@ def boys_weighted_sum(x, batch_off, batch_n, batch_kmax, w, w_off, out=None,
                       tol=None) -> torch.Tensor:
     """out[i] = sum_l w[w_off[b]+l] F_l(x[i]) for every argument i of batch b.
 
-    tol: None for the paper's tables, else as boys_eval_f64_tol (1e-10 or
-    more takes the screening tables)."""
+    tol: None for the 5e-14 tables of the current variant (set_tables), else
+    as boys_eval_f64_tol (1e-10 or more takes the screening tables)."""
     nb = _batch_args(x, batch_off, batch_n, batch_kmax, w, w_off)
     if out is None:
         out = torch.zeros_like(x)
@@ -231,6 +238,33 @@ def weighted_sum_get_config() -> int:
 
 def weighted_sum_set_config(config: int):
     _check(lib().boys_weighted_sum_set_config(config), "boys_weighted_sum_set_config")
+
+
+def set_tables(variant: int):
+    """Process-wide choice of the 5e-14 tables for orders up to 32:
+    TABLES_PAPER, TABLES_PER_KMAX or TABLES_CENTRE (boys_set_tables)."""
+    _check(lib().boys_set_tables(int(variant)), "boys_set_tables")
+
+
+def get_tables() -> int:
+    return int(lib().boys_get_tables())
+
+
+class table_variant:
+    """Context manager: calls inside use `variant`; the previous one is
+    restored on exit."""
+
+    def __init__(self, variant: int):
+        self.variant = int(variant)
+
+    def __enter__(self):
+        self.prev = get_tables()
+        set_tables(self.variant)
+        return self
+
+    def __exit__(self, *exc):
+        set_tables(self.prev)
+        return False
 
 
 def boys_backward(x: torch.Tensor, grad_f: torch.Tensor, kmax: int | None = None,

@@ -24,6 +24,11 @@ int check_device();
 // their workspace may have to grow, and a graph replayed later would share it.
 int check_not_capturing(hipStream_t stream);
 
+// The process-wide variant of the 5e-14 tables for orders up to 32
+// (boys_set_tables): BOYS_TABLES_PAPER, BOYS_TABLES_PER_KMAX or
+// BOYS_TABLES_CENTRE.
+int table_variant();
+
 // Frees the workspaces of boys_pairsum on every device (boys_finalize).
 void pairsum_release_all();
 

@@ -6,9 +6,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "boys_coeffs_f64.h"
 #include "boys_coeffs_f64_screen.h"
 #include "boys_coeffs_f64_high.h"
+#include "boys_coeffs_f64_perk.h"
+#include "boys_coeffs_f64_centre.h"
 
 namespace boys {
 
@@ -67,6 +71,101 @@ struct HighTables {
 static_assert(ScreenTables::kmax == kF64Kmax && HighTables::eps == PaperTables::eps,
               "the screening set covers the paper's orders; the high-order set its accuracy");
 
+// The paper's x0 and x1 and accuracy, with r_B and every r_{A,k} refitted at
+// the Walsh-table entry nearest the centre of the first feasible
+// anti-diagonal (n close to m), the alternative choice of Sec. II D.
+struct CentreTables {
+  static constexpr int kmax = BOYS_CTR_KMAX;
+  static constexpr double eps = BOYS_CTR_EPS;
+  static constexpr double x0 = BOYS_CTR_X0;
+  static constexpr double x1 = BOYS_CTR_X1;
+  static constexpr int rb_n = BOYS_CTR_RB_N, rb_m = BOYS_CTR_RB_M;
+  static constexpr int ra_n[kF64Kmax + 1] = BOYS_CTR_RA_DEG_N_INIT;
+  static constexpr int ra_m[kF64Kmax + 1] = BOYS_CTR_RA_DEG_M_INIT;
+  static constexpr double ra_p[kF64Kmax + 1][BOYS_CTR_RA_NMAX + 1] = BOYS_CTR_RA_P_INIT;
+  static constexpr double ra_q[kF64Kmax + 1][BOYS_CTR_RA_MMAX + 1] = BOYS_CTR_RA_Q_INIT;
+  static constexpr double rb_p[BOYS_CTR_RB_N + 1] = BOYS_CTR_RB_P_INIT;
+  static constexpr double rb_q[BOYS_CTR_RB_M + 1] = BOYS_CTR_RB_Q_INIT;
+};
+static_assert(CentreTables::kmax == kF64Kmax && CentreTables::x0 == PaperTables::x0 &&
+                  CentreTables::x1 == PaperTables::x1 && CentreTables::eps == PaperTables::eps,
+              "the centre set keeps the paper's regions and accuracy");
+
+// Per-kmax regions (Sec. II C): x0 and x1 follow from the highest order a
+// call evaluates, so a call that stops at K < 32 can use x0(K) and x1(K) of
+// its own K, with the two approximants such a call needs: r_B on
+// [x0(K), x1(K)] and r_{A,K} on [0, x0(K)].  Row K of every array belongs to
+// kmax = K (ra_* row K is r_{A,K} fitted on [0, x0(K)]); row 32 is the
+// paper's set.  A runtime-order kernel reading row k takes x0, x1 and r_B of
+// the same row.
+struct PerKmaxSet {
+  static constexpr int kmax = BOYS_PK_KMAX;
+  static constexpr double eps = BOYS_PK_EPS;
+  static constexpr double x0s[kF64Kmax + 1] = BOYS_PK_X0_INIT;
+  static constexpr double x1s[kF64Kmax + 1] = BOYS_PK_X1_INIT;
+  static constexpr int rb_ns[kF64Kmax + 1] = BOYS_PK_RB_N_INIT;
+  static constexpr int rb_ms[kF64Kmax + 1] = BOYS_PK_RB_M_INIT;
+  static constexpr double rb_ps[kF64Kmax + 1][BOYS_PK_RB_NMAX + 1] = BOYS_PK_RB_P_INIT;
+  static constexpr double rb_qs[kF64Kmax + 1][BOYS_PK_RB_MMAX + 1] = BOYS_PK_RB_Q_INIT;
+  static constexpr int ra_n[kF64Kmax + 1] = BOYS_PK_RA_N_INIT;
+  static constexpr int ra_m[kF64Kmax + 1] = BOYS_PK_RA_M_INIT;
+  static constexpr double ra_p[kF64Kmax + 1][BOYS_PK_RA_NMAX + 1] = BOYS_PK_RA_P_INIT;
+  static constexpr double ra_q[kF64Kmax + 1][BOYS_PK_RA_MMAX + 1] = BOYS_PK_RA_Q_INIT;
+};
+
+// The per-kmax set as a table set of one compile-time order K (the
+// write-out and pair kernels): row K's regions and r_B; r_{A,K} is row K of
+// ra_*, as for every set.
+template <int K>
+struct PerKmaxTables : PerKmaxSet {
+  static constexpr int kmax = K;
+  static constexpr double x0 = x0s[K];
+  static constexpr double x1 = x1s[K];
+  static constexpr int rb_n = rb_ns[K], rb_m = rb_ms[K];
+};
+
+// r_B's coefficient i of a table set: rb_p/rb_q, or row kmax of rb_ps/rb_qs
+// for the per-kmax set.  Read as an element of the two-dimensional array
+// with constant indices, the coefficients fold into instruction literals and
+// SGPR operands, as the fixed sets' do; read through a pointer to the row,
+// they became scalar loads hoisted out of the kernels' loops.
+template <class T, class = void>
+struct RbRows : std::false_type {};
+template <class T>
+struct RbRows<T, std::void_t<decltype(T::rb_ps)>> : std::true_type {};
+
+template <class T>
+__host__ __device__ constexpr double rb_p_at(int i) {
+  if constexpr (RbRows<T>::value) return T::rb_ps[T::kmax][i];
+  else return T::rb_p[i];
+}
+template <class T>
+__host__ __device__ constexpr double rb_q_at(int i) {
+  if constexpr (RbRows<T>::value) return T::rb_qs[T::kmax][i];
+  else return T::rb_q[i];
+}
+
+constexpr bool per_kmax_row32_is_the_papers() {
+  if (PerKmaxSet::x0s[kF64Kmax] != PaperTables::x0 || PerKmaxSet::x1s[kF64Kmax] != PaperTables::x1)
+    return false;
+  if (PerKmaxSet::rb_ns[kF64Kmax] != PaperTables::rb_n || PerKmaxSet::rb_ms[kF64Kmax] != PaperTables::rb_m)
+    return false;
+  for (int i = 0; i <= PaperTables::rb_n; ++i)
+    if (PerKmaxSet::rb_ps[kF64Kmax][i] != PaperTables::rb_p[i]) return false;
+  for (int i = 0; i <= PaperTables::rb_m; ++i)
+    if (PerKmaxSet::rb_qs[kF64Kmax][i] != PaperTables::rb_q[i]) return false;
+  const int n = PaperTables::ra_n[kF64Kmax], m = PaperTables::ra_m[kF64Kmax];
+  if (PerKmaxSet::ra_n[kF64Kmax] != n || PerKmaxSet::ra_m[kF64Kmax] != m) return false;
+  for (int i = 0; i <= n; ++i)
+    if (PerKmaxSet::ra_p[kF64Kmax][i] != PaperTables::ra_p[kF64Kmax][i]) return false;
+  for (int i = 0; i <= m; ++i)
+    if (PerKmaxSet::ra_q[kF64Kmax][i] != PaperTables::ra_q[kF64Kmax][i]) return false;
+  return true;
+}
+static_assert(PerKmaxSet::kmax == kF64Kmax && PerKmaxSet::eps == PaperTables::eps &&
+                  per_kmax_row32_is_the_papers(),
+              "the per-kmax set covers the paper's orders at its accuracy; row 32 is the paper's set");
+
 // The table set for a caller's order and error tolerance: the cheapest set
 // that covers kmax and whose guarantee is at most tol (1 = screening, 0 = the
 // paper's, 2 = high orders), or -1 if none does (tol below 5e-14 or NaN, or
@@ -103,22 +202,30 @@ __device__ __forceinline__ double rational_a(double x) {
   double p = T::ra_p[K][n];
 #pragma unroll
   for (int i = n - 1; i >= 0; --i) p = __builtin_fma(p, x, T::ra_p[K][i]);
-  double q = x + T::ra_q[K][m - 1];
+  if constexpr (m == 0) {
+    return p;  // monic of degree 0: q = 1
+  } else {
+    double q = x + T::ra_q[K][m - 1];
 #pragma unroll
-  for (int i = m - 2; i >= 0; --i) q = __builtin_fma(q, x, T::ra_q[K][i]);
-  return p / q;
+    for (int i = m - 2; i >= 0; --i) q = __builtin_fma(q, x, T::ra_q[K][i]);
+    return p / q;
+  }
 }
 
 // r_B(x): F_0 on [x0, x1].
 template <class T = PaperTables>
 __device__ __forceinline__ double rational_b(double x) {
-  double p = T::rb_p[T::rb_n];
+  double p = rb_p_at<T>(T::rb_n);
 #pragma unroll
-  for (int i = T::rb_n - 1; i >= 0; --i) p = __builtin_fma(p, x, T::rb_p[i]);
-  double q = x + T::rb_q[T::rb_m - 1];
+  for (int i = T::rb_n - 1; i >= 0; --i) p = __builtin_fma(p, x, rb_p_at<T>(i));
+  if constexpr (T::rb_m == 0) {
+    return p;
+  } else {
+    double q = x + rb_q_at<T>(T::rb_m - 1);
 #pragma unroll
-  for (int i = T::rb_m - 2; i >= 0; --i) q = __builtin_fma(q, x, T::rb_q[i]);
-  return p / q;
+    for (int i = T::rb_m - 2; i >= 0; --i) q = __builtin_fma(q, x, rb_q_at<T>(i));
+    return p / q;
+  }
 }
 
 // Negative arguments (outside the domain) become NaN, which then flows

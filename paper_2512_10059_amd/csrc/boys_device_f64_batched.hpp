@@ -117,21 +117,29 @@ __device__ __forceinline__ double rational_a_t(double x) {
   double p = T::ra_p[K][n];
 #pragma unroll
   for (int i = n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::ra_p[K][i]);
-  double q = x + T::ra_q[K][m - 1];
+  if constexpr (m == 0) {
+    return p;  // monic of degree 0: q = 1
+  } else {
+    double q = x + T::ra_q[K][m - 1];
 #pragma unroll
-  for (int i = m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::ra_q[K][i]);
-  return p / q;
+    for (int i = m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::ra_q[K][i]);
+    return p / q;
+  }
 }
 
 template <class T>
 __device__ __forceinline__ double rational_b_t(double x) {
-  double p = T::rb_p[T::rb_n];
+  double p = rb_p_at<T>(T::rb_n);
 #pragma unroll
-  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::rb_p[i]);
-  double q = x + T::rb_q[T::rb_m - 1];
+  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, rb_p_at<T>(i));
+  if constexpr (T::rb_m == 0) {
+    return p;
+  } else {
+    double q = x + rb_q_at<T>(T::rb_m - 1);
 #pragma unroll
-  for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::rb_q[i]);
-  return p / q;
+    for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, rb_q_at<T>(i));
+    return p / q;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -185,10 +193,16 @@ static_assert(RtRows<PaperTables>::pad_n == BOYS_RA_NMAX && RtRows<PaperTables>:
               "the paper's rows take the (8, 13) and (8, 9) passes");
 static __constant__ const RtRows<PaperTables> kRaRows = make_rt_rows<PaperTables>();
 static __constant__ const RtRows<ScreenTables> kRaRowsScreen = make_rt_rows<ScreenTables>();
+static __constant__ const RtRows<CentreTables> kRaRowsCentre = make_rt_rows<CentreTables>();
+static_assert(monic_rows<CentreTables>(), "denominators are monic");
 
 template <class T>
 __device__ __forceinline__ const RtRows<T> &rt_rows() {
+  static_assert(std::is_same_v<T, PaperTables> || std::is_same_v<T, ScreenTables> ||
+                    std::is_same_v<T, CentreTables>,
+                "runtime rows exist for the sets of fixed regions");
   if constexpr (std::is_same_v<T, ScreenTables>) return kRaRowsScreen;
+  else if constexpr (std::is_same_v<T, CentreTables>) return kRaRowsCentre;
   else return kRaRows;
 }
 
@@ -237,17 +251,106 @@ __device__ __forceinline__ double rational_a_rt_pos(double x, int k) {
   return rational_loaded_pos<R::pad_n, R::hi_m>(x, P, Q);
 }
 
+// r_{A,K} of a table set with div_positive for the quotient (literal
+// coefficients, SGPR addends, as rational_a_t).
+template <int K, class T>
+__device__ __forceinline__ double rational_a_lit_pos(double x) {
+  constexpr int n = T::ra_n[K], m = T::ra_m[K];
+  double p = T::ra_p[K][n];
+#pragma unroll
+  for (int i = n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::ra_p[K][i]);
+  if constexpr (m == 0) {
+    return p;
+  } else {
+    double q = x + T::ra_q[K][m - 1];
+#pragma unroll
+    for (int i = m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::ra_q[K][i]);
+    return div_positive(p, q);
+  }
+}
+
 // r_B of a table set with div_positive for the quotient (literal
 // coefficients, SGPR addends, as rational_b_t).
 template <class T>
 __device__ __forceinline__ double rational_b_lit_pos(double x) {
-  double p = T::rb_p[T::rb_n];
+  double p = rb_p_at<T>(T::rb_n);
 #pragma unroll
-  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, T::rb_p[i]);
-  double q = x + T::rb_q[T::rb_m - 1];
+  for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, rb_p_at<T>(i));
+  if constexpr (T::rb_m == 0) {
+    return p;
+  } else {
+    double q = x + rb_q_at<T>(T::rb_m - 1);
 #pragma unroll
-  for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, T::rb_q[i]);
-  return div_positive(p, q);
+    for (int i = T::rb_m - 2; i >= 0; --i) q = fma_uniform_addend(q, x, rb_q_at<T>(i));
+    return div_positive(p, q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The batched consumer's view of a table set for a batch of order k: the
+// region ends and the two approximants.  Sets with fixed regions use their
+// x0 and x1, r_{A,k} from the runtime rows above and the literal-coded r_B.
+// The per-kmax set takes x0, x1 and r_B of row k as well, so both rationals
+// change with k; they are reached by a binary dispatch on the wave-uniform k
+// (five or six scalar compares and branches per call) to literal-coded
+// passes of each row's exact degrees.  Padding the rows to common lengths
+// instead, as for the fixed sets' region A, would add 10-45% to the
+// rationals' steps: the rows' (n, m) vary more than the paper's.
+#define BOYS_ORDER_CASE(K) \
+  case K:                   \
+    return f(std::integral_constant<int, K>{});
+template <class F>
+__device__ __forceinline__ double order_dispatch(int k, const F &f) {
+  static_assert(kF64Kmax == 32, "one case per order 0..32");
+  switch (k) {
+    BOYS_ORDER_CASE(0) BOYS_ORDER_CASE(1) BOYS_ORDER_CASE(2) BOYS_ORDER_CASE(3) BOYS_ORDER_CASE(4)
+    BOYS_ORDER_CASE(5) BOYS_ORDER_CASE(6) BOYS_ORDER_CASE(7) BOYS_ORDER_CASE(8) BOYS_ORDER_CASE(9)
+    BOYS_ORDER_CASE(10) BOYS_ORDER_CASE(11) BOYS_ORDER_CASE(12) BOYS_ORDER_CASE(13)
+    BOYS_ORDER_CASE(14) BOYS_ORDER_CASE(15) BOYS_ORDER_CASE(16) BOYS_ORDER_CASE(17)
+    BOYS_ORDER_CASE(18) BOYS_ORDER_CASE(19) BOYS_ORDER_CASE(20) BOYS_ORDER_CASE(21)
+    BOYS_ORDER_CASE(22) BOYS_ORDER_CASE(23) BOYS_ORDER_CASE(24) BOYS_ORDER_CASE(25)
+    BOYS_ORDER_CASE(26) BOYS_ORDER_CASE(27) BOYS_ORDER_CASE(28) BOYS_ORDER_CASE(29)
+    BOYS_ORDER_CASE(30) BOYS_ORDER_CASE(31)
+    default:
+      return f(std::integral_constant<int, 32>{});
+  }
+}
+#undef BOYS_ORDER_CASE
+
+template <class T>
+constexpr bool kPerKmaxRows = std::is_same_v<T, PerKmaxSet>;
+
+template <class T>
+__device__ __forceinline__ double batch_x0(int k) {
+  if constexpr (kPerKmaxRows<T>) return PerKmaxSet::x0s[k];
+  else return T::x0;
+}
+
+template <class T>
+__device__ __forceinline__ double batch_x1(int k) {
+  if constexpr (kPerKmaxRows<T>) return PerKmaxSet::x1s[k];
+  else return T::x1;
+}
+
+template <class T>
+__device__ __forceinline__ double batch_rational_a(double x, int k) {
+  if constexpr (kPerKmaxRows<T>) {
+    return order_dispatch(k, [x](auto K) {
+      return rational_a_lit_pos<decltype(K)::value, PerKmaxTables<decltype(K)::value>>(x);
+    });
+  } else {
+    return rational_a_rt_pos<T>(x, k);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ double batch_rational_b(double x, int k) {
+  if constexpr (kPerKmaxRows<T>) {
+    return order_dispatch(
+        k, [x](auto K) { return rational_b_lit_pos<PerKmaxTables<decltype(K)::value>>(x); });
+  } else {
+    return rational_b_lit_pos<T>(x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -321,7 +424,7 @@ __device__ __forceinline__ double fma_step(double h, double t, double c) {
 template <int CH, class T = PaperTables>
 __device__ __forceinline__ double wsum_sweep_a(double x, int k, const wpair *ta) {
   const double e = exp_neg(x);
-  const double S = rational_a_rt_pos<T>(x, k);
+  const double S = batch_rational_a<T>(x, k);
   const double two_x = x + x;
   const int steps = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
   const wpair *t = ta + (kSweepPadA + k + 1 - steps);
@@ -346,7 +449,7 @@ template <int CH, class T = PaperTables>
 __device__ __forceinline__ double wsum_sweep_b(double x, int k, const wpair *tb) {
   const double e = exp_neg(x);
   const double g = 0.5 * recip(x);
-  const double S = rational_b_lit_pos<T>(x);
+  const double S = batch_rational_b<T>(x, k);
   const int top = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
   double z = 0.0, v = 0.0;
   for (int l0 = top; l0 > 0; l0 -= CH) {

@@ -108,6 +108,17 @@ constexpr auto make_table(std::index_sequence<K...>) {
 constexpr auto kEvalTable = make_table<PaperTables>(std::make_index_sequence<kF64Kmax + 1>{});
 constexpr auto kEvalTableScreen =
     make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kEvalTableCentre =
+    make_table<CentreTables>(std::make_index_sequence<kF64Kmax + 1>{});
+
+// The per-kmax regions: order K with row K of the per-kmax set (row 32 is
+// the paper's set, so K = 32 takes the paper's kernel).
+template <std::size_t... K>
+constexpr auto make_per_kmax_table(std::index_sequence<K...>) {
+  return std::array<EvalKernel, sizeof...(K) + 1>{
+      {&eval_f64_kernel<int(K), PerKmaxTables<int(K)>>..., &eval_f64_kernel<kF64Kmax, PaperTables>}};
+}
+constexpr auto kEvalTablePerKmax = make_per_kmax_table(std::make_index_sequence<kF64Kmax>{});
 
 // Orders above 32: the high-order set (its orders up to 32 are not needed:
 // the paper's tables cover them at the same accuracy).
@@ -144,9 +155,11 @@ extern "C" int boys_eval_f64_tol(const double *x, int64_t n, int kmax, double to
   const int block = 64 * eval_waves(kmax);
   int64_t blocks = (n + block - 1) / block;
   if (blocks > kMaxBlocks) blocks = kMaxBlocks;
-  const EvalKernel kernel = set == kSetHigh     ? kEvalTableHigh[kmax - kF64Kmax - 1]
-                           : set == kSetScreen ? kEvalTableScreen[kmax]
-                                               : kEvalTable[kmax];
+  EvalKernel kernel = kEvalTable[kmax < kF64Kmax ? kmax : kF64Kmax];
+  if (set == kSetHigh) kernel = kEvalTableHigh[kmax - kF64Kmax - 1];
+  else if (set == kSetScreen) kernel = kEvalTableScreen[kmax];
+  else if (table_variant() == BOYS_TABLES_PER_KMAX) kernel = kEvalTablePerKmax[kmax];
+  else if (table_variant() == BOYS_TABLES_CENTRE) kernel = kEvalTableCentre[kmax];
   hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(block), 0, stream, x, n, out, ld_out,
                      contiguous);
   return hip_status(hipGetLastError());

@@ -163,6 +163,15 @@ constexpr auto make_table(std::index_sequence<K...>) {
 }
 constexpr auto kPairTable = make_table<PaperTables>(std::make_index_sequence<kF64Kmax + 1>{});
 constexpr auto kPairTableScreen = make_table<ScreenTables>(std::make_index_sequence<kF64Kmax + 1>{});
+constexpr auto kPairTableCentre = make_table<CentreTables>(std::make_index_sequence<kF64Kmax + 1>{});
+// The per-kmax regions: order K with row K of the per-kmax set (row 32 is
+// the paper's set, so K = 32 takes the paper's kernel).
+template <std::size_t... K>
+constexpr auto make_per_kmax_table(std::index_sequence<K...>) {
+  return std::array<PairKernel, sizeof...(K) + 1>{
+      {&pairsum_kernel<int(K), PerKmaxTables<int(K)>>..., &pairsum_kernel<kF64Kmax, PaperTables>}};
+}
+constexpr auto kPairTablePerKmax = make_per_kmax_table(std::make_index_sequence<kF64Kmax>{});
 // Orders 33..40: the high-order set.
 template <std::size_t... I>
 constexpr auto make_high_table(std::index_sequence<I...>) {
@@ -300,9 +309,11 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
-  const PairKernel kernel = set == kSetHigh     ? kPairTableHigh[kmax - kF64Kmax - 1]
-                           : set == kSetScreen ? kPairTableScreen[kmax]
-                                               : kPairTable[kmax];
+  PairKernel kernel = kPairTable[kmax < kF64Kmax ? kmax : kF64Kmax];
+  if (set == kSetHigh) kernel = kPairTableHigh[kmax - kF64Kmax - 1];
+  else if (set == kSetScreen) kernel = kPairTableScreen[kmax];
+  else if (table_variant() == BOYS_TABLES_PER_KMAX) kernel = kPairTablePerKmax[kmax];
+  else if (table_variant() == BOYS_TABLES_CENTRE) kernel = kPairTableCentre[kmax];
   hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);

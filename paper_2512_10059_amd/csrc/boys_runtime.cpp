@@ -1,6 +1,7 @@
 // Status codes, error capture and device checks of libboys.so.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <mutex>
 
@@ -15,7 +16,10 @@ constexpr int kMaxDevices = 64;
 // 0 = unknown, 1 = gfx950, -1 = other architecture.
 int g_arch_ok[kMaxDevices] = {0};
 std::mutex g_arch_mutex;
+std::atomic<int> g_table_variant{BOYS_TABLES_PAPER};
 }  // namespace
+
+int table_variant() { return g_table_variant.load(std::memory_order_relaxed); }
 
 int hip_status(hipError_t err) {
   if (err == hipSuccess) return BOYS_OK;
@@ -65,5 +69,14 @@ const char *boys_strerror(int status) {
 }
 
 int boys_last_hip_error(void) { return boys::g_last_hip_error; }
+
+int boys_set_tables(int variant) {
+  if (variant != BOYS_TABLES_PAPER && variant != BOYS_TABLES_PER_KMAX && variant != BOYS_TABLES_CENTRE)
+    return BOYS_EINVAL;
+  boys::g_table_variant.store(variant, std::memory_order_relaxed);
+  return BOYS_OK;
+}
+
+int boys_get_tables(void) { return boys::table_variant(); }
 
 }  // extern "C"

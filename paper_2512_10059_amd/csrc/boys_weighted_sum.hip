@@ -361,6 +361,10 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
     const int64_t rem = int64_t(f.n) - j * T;
     const int count = int(rem < T ? rem : T);
     const int k = f.k;
+    // Region ends of this batch (the set's own, or row k's for the per-kmax
+    // set): uniform, so they stay in scalar registers.
+    const double x0v = batch_x0<TS>(k);
+    const double x1v = batch_x1<TS>(k);
     ++j;
     if (reload) {
       wave_sync();  // the previous batch's passes have read the tables
@@ -409,8 +413,8 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
           const uint64_t valid = kFull ? ~uint64_t(0) : lane_prefix_mask(count - it * 64);
-          nA += __popcll(__ballot(xv[it] < TS::x0) & valid);
-          nC += __popcll(__ballot(region_c<TS>(xv[it])) & valid);
+          nA += __popcll(__ballot(xv[it] < x0v) & valid);
+          nC += __popcll(__ballot(xv[it] > x1v) & valid);
         }
         int bA = 0, bC = nA, bB = nA + nC;
 #pragma unroll
@@ -420,8 +424,8 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
           double xr = xv[it];
           asm volatile("" : "+v"(xr));
           const uint64_t valid = kFull ? ~uint64_t(0) : lane_prefix_mask(count - it * 64);
-          const bool isA = xr < TS::x0;
-          const bool isC = region_c<TS>(xr);  // x1 > x0: never with isA
+          const bool isA = xr < x0v;
+          const bool isC = xr > x1v;  // C = (x1, inf); x1 > x0: never with isA
           const uint64_t mA = __ballot(isA) & valid;
           const uint64_t mC = __ballot(isC) & valid;
           const int rA = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mA >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mA), 0u)));
@@ -487,8 +491,8 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
         if (p < count) {
           const double xq = xv[it];
           double acc;
-          if (xq < TS::x0) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
-          else if (region_c<TS>(xq)) acc = wsum_region_c(xq, k, tc);
+          if (xq < x0v) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
+          else if (xq > x1v) acc = wsum_region_c(xq, k, tc);
           else acc = wsum_sweep_b<CH, TS>(xq, k, tb);
           a.out[first + p] = acc;
         }
@@ -503,9 +507,24 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
 
 using WsKernel = void (*)(WsArgs);
 
+// The table sets of the batched consumer: the paper's, the screening set
+// (eps_tol = 1e-10), the per-kmax regions and the centre-of-anti-diagonal
+// refit (boys_set_tables).
+enum WsSet { kWsPaper = 0, kWsScreen = 1, kWsPerKmax = 2, kWsCentre = 3, kWsSets = 4 };
+
+// The set for a call at tolerance tol (>= 5e-14): the screening set from
+// 1e-10 on, else the process-wide variant of the 5e-14 tables.
+int ws_set_for(double tol) {
+  if (tol >= ScreenTables::eps) return kWsScreen;
+  switch (table_variant()) {
+    case BOYS_TABLES_PER_KMAX: return kWsPerKmax;
+    case BOYS_TABLES_CENTRE: return kWsCentre;
+    default: return kWsPaper;
+  }
+}
+
 struct WsConfig {
-  WsKernel kernel;         // the paper's tables
-  WsKernel kernel_screen;  // the screening tables (eps_tol = 1e-10)
+  WsKernel kernel[kWsSets];  // by WsSet
   int items;               // arguments per lane per tile (tile = 64 * items)
   int bin;                 // region binning in LDS
   int chunk;               // sweep chunk (orders whose constants are read together)
@@ -515,8 +534,10 @@ struct WsConfig {
 };
 
 // Grids are counted in rounds of resident workgroups.
-#define BOYS_WS_CONFIG(ITEMS, BIN, CH, R, TAPER, NAME) \
-  {&ws_kernel<ITEMS, BIN, CH, PaperTables>, &ws_kernel<ITEMS, BIN, CH, ScreenTables>, ITEMS, BIN, CH, R, TAPER, NAME}
+#define BOYS_WS_CONFIG(ITEMS, BIN, CH, R, TAPER, NAME)                                   \
+  {{&ws_kernel<ITEMS, BIN, CH, PaperTables>, &ws_kernel<ITEMS, BIN, CH, ScreenTables>,    \
+    &ws_kernel<ITEMS, BIN, CH, PerKmaxSet>, &ws_kernel<ITEMS, BIN, CH, CentreTables>}, \
+   ITEMS, BIN, CH, R, TAPER, NAME}
 const WsConfig kConfigs[] = {
     BOYS_WS_CONFIG(8, true, 4, 3, 2, "tile512-bin-ch4-3rounds-taper2"),
     BOYS_WS_CONFIG(8, true, 4, 3, 0, "tile512-bin-ch4-3rounds"),
@@ -541,7 +562,7 @@ struct GraphKey {
   const void *ptrs[7];
   int32_t nbatch;
   int config;
-  int set;  // 0: the paper's tables, 1: the screening tables
+  int set;  // WsSet
   const void *ws;
   bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -573,11 +594,11 @@ struct DeviceState {
   // one.
   std::vector<void *> retired;
   std::vector<RetiredGraph> retired_graphs;
-  GraphSlot slot[2][kNumConfigs];  // [table set][configuration]
+  GraphSlot slot[kWsSets][kNumConfigs];  // [table set][configuration]
   int config = -1;  // -1: not chosen yet (one choice serves both sets)
   int cus = 0;
   char arch[32] = {};  // the device's architecture name (up to the first ':')
-  int resident[2][kNumConfigs] = {};  // workgroups per CU, 0: not queried yet
+  int resident[kWsSets][kNumConfigs] = {};  // workgroups per CU, 0: not queried yet
   void *scratch_ptr = nullptr;         // this device's copy of `scratch`
   bool has_graphs() const {
     for (const auto &row : slot)
@@ -755,7 +776,7 @@ int main_grid(DeviceState &s, int cfg, int set, unsigned *grid) {
   const WsConfig &conf = kConfigs[cfg];
   int &resident = s.resident[set][cfg];
   if (resident == 0) {
-    const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
+    const WsKernel kern = conf.kernel[set];
     int r = 0;
     BOYS_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, reinterpret_cast<const void *>(kern),
                                                               kWsBlock, 0));
@@ -803,7 +824,7 @@ int prepare_graph(DeviceState &s, const Call &c, int cfg, int set, hipStream_t s
   WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, tile_start, cost_start, c.nbatch, conf.taper};
   void *main_args[] = {&args};
   hipKernelNodeParams mp = {};
-  const WsKernel kern = set ? conf.kernel_screen : conf.kernel;
+  const WsKernel kern = conf.kernel[set];
   unsigned grid = 0;
   if (int st = main_grid(s, cfg, set, &grid)) return st;
   mp.gridDim = dim3(grid);
@@ -897,17 +918,18 @@ int scratch_address(DeviceState &s, void **out) {
   return BOYS_OK;
 }
 
-int launch_direct(DeviceState &s, const Call &c, int cfg, const Workspace &ws, hipStream_t stream) {
+int launch_direct(DeviceState &s, const Call &c, int cfg, int set, const Workspace &ws,
+                  hipStream_t stream) {
   const WsConfig &conf = kConfigs[cfg];
   const int tile_shift = __builtin_ctz(unsigned(64 * conf.items));
   unsigned grid = 0;
-  if (int st = main_grid(s, cfg, 0, &grid)) return st;
+  if (int st = main_grid(s, cfg, set, &grid)) return st;
   hipLaunchKernelGGL(ws_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, c.bn, c.bk, c.nbatch,
                      tile_shift, ws.tile_start, ws.cost_start);
   BOYS_TRY_HIP(hipGetLastError());
   const WsArgs args{c.x, c.boff, c.bn, c.bk, c.w, c.woff, c.out, ws.tile_start, ws.cost_start, c.nbatch,
                     conf.taper};
-  hipLaunchKernelGGL(conf.kernel, dim3(grid), dim3(kWsBlock), 0, stream, args);
+  hipLaunchKernelGGL(conf.kernel[set], dim3(grid), dim3(kWsBlock), 0, stream, args);
   BOYS_TRY_HIP(hipGetLastError());
   return BOYS_OK;
 }
@@ -932,15 +954,15 @@ int boys_weighted_sum_noalloc(const double *x, const int64_t *batch_off, const i
   void *base = nullptr;
   if (int st = scratch_address(*s, &base)) return st;
   const int cfg = s->config < 0 ? kDefaultConfig : s->config;
-  return launch_direct(*s, c, cfg, carve(base, kNoAllocCap), stream);
+  return launch_direct(*s, c, cfg, ws_set_for(PaperTables::eps), carve(base, kNoAllocCap), stream);
 }
 
 int boys_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
                       const int32_t *batch_kmax, const double *w, const int64_t *w_off,
                       int32_t nbatch, double *out, hipStream_t stream) {
   using namespace boys;
-  return weighted_sum_with_set(Call{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out}, 0,
-                               stream);
+  return weighted_sum_with_set(Call{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out},
+                               ws_set_for(PaperTables::eps), stream);
 }
 
 int boys_weighted_sum_tol(const double *x, const int64_t *batch_off, const int32_t *batch_n,
@@ -950,7 +972,7 @@ int boys_weighted_sum_tol(const double *x, const int64_t *batch_off, const int32
   const int set = table_set_for(kF64Kmax, tol);
   if (set < 0) return BOYS_EINVAL;
   return weighted_sum_with_set(Call{x, batch_off, batch_n, batch_kmax, w, w_off, nbatch, out},
-                               set == kSetScreen ? 1 : 0, stream);
+                               ws_set_for(tol), stream);
 }
 
 int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int32_t *batch_n,
@@ -977,15 +999,16 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   // them one after another would favour the first ones, measured while the
   // clocks are still at their boost level.
   constexpr int kRounds = 3;
+  const int set = ws_set_for(PaperTables::eps);  // the variant of the paper's accuracy in use
   float tmin[kNumConfigs] = {};
   int st = BOYS_OK;
   for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg)
-    st = launch(*s, c, cfg, 0, stream);  // warm-up (and graph build)
+    st = launch(*s, c, cfg, set, stream);  // warm-up (and graph build)
   for (int r = 0; r < kRounds && st == BOYS_OK; ++r) {
     for (int cfg = 0; cfg < kNumConfigs && st == BOYS_OK; ++cfg) {
       float t = 0.0f;
       if ((st = hip_status(hipEventRecord(e0, stream)))) break;
-      if ((st = launch(*s, c, cfg, 0, stream))) break;
+      if ((st = launch(*s, c, cfg, set, stream))) break;
       if ((st = hip_status(hipEventRecord(e1, stream)))) break;
       if ((st = hip_status(hipEventSynchronize(e1)))) break;
       if ((st = hip_status(hipEventElapsedTime(&t, e0, e1)))) break;
@@ -1000,8 +1023,8 @@ int boys_tune_weighted_sum(const double *x, const int64_t *batch_off, const int3
   (void)hipEventDestroy(e1);
   if (st != BOYS_OK) return st;
   s->config = best;
-  store_config(s->arch, nbatch, 0, best);
-  if ((st = launch(*s, c, best, 0, stream))) return st;  // leaves the graph of the winner cached
+  store_config(s->arch, nbatch, set, best);
+  if ((st = launch(*s, c, best, set, stream))) return st;  // leaves the graph of the winner cached
   if (best_config) *best_config = best;
   if (best_ms) *best_ms = best_t;
   return BOYS_OK;

@@ -116,3 +116,18 @@ def test_tolerance_argument_errors_without_gpu(lib):
     for tol in (1e-15, float("nan")):
         assert b(dummy, dummy, 10, 5, 6, tol, dummy, None) == EINVAL
     assert b(dummy, dummy, 0, 5, 6, 1e-10, dummy, None) == 0
+
+
+def test_table_variant_setting_without_gpu(lib):
+    """boys_set_tables takes the three variants, rejects anything else without
+    changing the current one, and boys_get_tables reports it (host only)."""
+    lib.boys_set_tables.argtypes = [ctypes.c_int]
+    assert lib.boys_get_tables() == 0  # the paper's tables by default
+    for v in (1, 2, 0):
+        assert lib.boys_set_tables(v) == 0
+        assert lib.boys_get_tables() == v
+    assert lib.boys_set_tables(2) == 0
+    for bad in (-1, 3, 99):
+        assert lib.boys_set_tables(bad) == EINVAL
+        assert lib.boys_get_tables() == 2
+    assert lib.boys_set_tables(0) == 0
