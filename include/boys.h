@@ -245,8 +245,9 @@ BOYS_API int boys_weighted_sum_tol(const double *x, const int64_t *batch_off,
 
 /*
  * Times every configuration of the persistent kernel (tile length, region
- * binning on or off, sweep chunk, grid of 2 to 4 rounds of resident
- * workgroups, equal or tapered per-wave shares) on these arguments (each run
+ * binning on or off, sweep chunk, register prefetch of the next tile, grid
+ * of 2 to 4 rounds of resident workgroups, equal or tapered per-wave
+ * shares) on these arguments (each run
  * writes out) with the 5e-14 tables of the current boys_set_tables variant,
  * keeps the fastest for later boys_weighted_sum calls on this device, and
  * reports it.  Synchronises `stream`.  best_config (may be NULL)

@@ -313,7 +313,12 @@ constexpr int kWsBlock = 64 * kWsWaves;
 // the two region boundaries.  CH is the sweep chunk: the constant pairs of
 // CH orders are read together, so a chunk waits for LDS once.  No workgroup
 // barrier follows the set-up.
-template <int ITEMS, bool BIN, int CH, class TS>
+//
+// With PF the wave loads the next tile's arguments of the same batch into
+// registers right after taking the current tile's, so their latency hides
+// behind the current tile's binning, passes and stores (8 more VGPR pairs
+// at tile 512).
+template <int ITEMS, bool BIN, int CH, class TS, bool PF = false>
 __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
   static_assert((ITEMS & (ITEMS - 1)) == 0, "tiles are powers of two: the scan counts them by shifts");
   static_assert(CH <= kChunkMax, "the tables are padded for chunks up to kChunkMax");
@@ -348,6 +353,8 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
     j = (lo - f.cost0 + cost - 1) / cost;
   }
   bool reload = true;
+  double xn[ITEMS];        // PF: the next tile's arguments
+  bool have_next = false;  // PF: xn holds the tile this iteration takes
 
   for (;;) {
     while (b < a.nbatch && j >= f.tiles) {  // past this batch: next non-empty one
@@ -379,7 +386,10 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
     // are never evaluated or stored.
     const char *const tx = reinterpret_cast<const char *>(a.x + first);
     double xv[ITEMS];
-    if (count == T) {
+    if (PF && have_next) {
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) xv[it] = xn[it];
+    } else if (count == T) {
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it)
         xv[it] = *reinterpret_cast<const double *>(tx + (lane8 + uint32_t(it) * 512u));
@@ -389,6 +399,23 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
       for (int it = 0; it < ITEMS; ++it) {
         const uint32_t o = lane8 + uint32_t(it) * 512u;
         xv[it] = *reinterpret_cast<const double *>(tx + (o < last8 ? o : last8));
+      }
+    }
+    if constexpr (PF) {
+      // The next tile (j, after the increment above) when it is in this
+      // batch and starts inside this wave's share: exactly the tile the next
+      // iteration takes, since neither the batch advance nor the share test
+      // then fires.  Offsets clamped as for a partial tile.
+      have_next = j < f.tiles && f.cost0 + j * ITEMS * pass_cost(k) < hi;
+      if (have_next) {
+        const int64_t nrem = int64_t(f.n) - j * T;
+        const uint32_t nlast8 = uint32_t((nrem < T ? nrem : T) - 1) * 8u;
+        const char *const nx = reinterpret_cast<const char *>(a.x + f.off + j * T);
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          const uint32_t o = lane8 + uint32_t(it) * 512u;
+          xn[it] = *reinterpret_cast<const double *>(nx + (o < nlast8 ? o : nlast8));
+        }
       }
     }
 #pragma unroll
@@ -534,10 +561,11 @@ struct WsConfig {
 };
 
 // Grids are counted in rounds of resident workgroups.
-#define BOYS_WS_CONFIG(ITEMS, BIN, CH, R, TAPER, NAME)                                   \
-  {{&ws_kernel<ITEMS, BIN, CH, PaperTables>, &ws_kernel<ITEMS, BIN, CH, ScreenTables>,    \
-    &ws_kernel<ITEMS, BIN, CH, PerKmaxSet>, &ws_kernel<ITEMS, BIN, CH, CentreTables>}, \
+#define BOYS_WS_CONFIG_PF(ITEMS, BIN, CH, PF, R, TAPER, NAME)                                         \
+  {{&ws_kernel<ITEMS, BIN, CH, PaperTables, PF>, &ws_kernel<ITEMS, BIN, CH, ScreenTables, PF>,         \
+    &ws_kernel<ITEMS, BIN, CH, PerKmaxSet, PF>, &ws_kernel<ITEMS, BIN, CH, CentreTables, PF>}, \
    ITEMS, BIN, CH, R, TAPER, NAME}
+#define BOYS_WS_CONFIG(ITEMS, BIN, CH, R, TAPER, NAME) BOYS_WS_CONFIG_PF(ITEMS, BIN, CH, false, R, TAPER, NAME)
 const WsConfig kConfigs[] = {
     BOYS_WS_CONFIG(8, true, 4, 3, 2, "tile512-bin-ch4-3rounds-taper2"),
     BOYS_WS_CONFIG(8, true, 4, 3, 0, "tile512-bin-ch4-3rounds"),
@@ -549,8 +577,12 @@ const WsConfig kConfigs[] = {
     BOYS_WS_CONFIG(8, true, 8, 3, 3, "tile512-bin-ch8-3rounds-taper3"),
     BOYS_WS_CONFIG(4, true, 4, 3, 2, "tile256-bin-ch4-3rounds-taper2"),
     BOYS_WS_CONFIG(4, false, 4, 2, 0, "tile256-nobin-ch4-2rounds"),
+    BOYS_WS_CONFIG_PF(8, true, 4, true, 2, 3, "tile512-bin-ch4-pf-2rounds-taper3"),
+    BOYS_WS_CONFIG_PF(8, true, 4, true, 3, 3, "tile512-bin-ch4-pf-3rounds-taper3"),
+    BOYS_WS_CONFIG_PF(4, true, 4, true, 3, 3, "tile256-bin-ch4-pf-3rounds-taper3"),
 };
 #undef BOYS_WS_CONFIG
+#undef BOYS_WS_CONFIG_PF
 constexpr int kNumConfigs = int(sizeof(kConfigs) / sizeof(kConfigs[0]));
 constexpr int kDefaultConfig = 0;  // tile512-bin-ch4-3rounds-taper2
 
