@@ -84,7 +84,7 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
   if (x < T::x0) {
     const double e = pair_exp(x, eij);
     const double two_x = x + x;
-    double F = rational_a_t<K, T>(x);
+    double F = rational_a_lit_pos<K, T>(x);
     acc = cw.c[K] * F;
 #pragma unroll
     for (int l = K - 1; l >= 0; --l) {
@@ -103,7 +103,7 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
   } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l)
     const double e = pair_exp(x, eij);
     const double g = 0.5 * recip(x);
-    const double F0 = rational_b_t<T>(x);
+    const double F0 = rational_b_lit_pos<T>(x);
     // Chunks of four steps (one chunk rolled), so at most four coefficient
     // pairs are in registers; K % 4 leading steps first.
     double P = pq[K].x, Q = pq[K].y;

@@ -121,3 +121,18 @@ def test_paper_size_sampled_rows():
     rows = np.random.default_rng(6).choice(x.size, 16, replace=False)
     check(x, y, c, z, rows)
     assert np.all(np.isfinite(z))
+
+
+def test_operands_outside_the_factor_range():
+    """e^-(x_i + x_j) is formed as e^-x_i e^-x_j only for operands in
+    [0, 700]; pairs with a negative or a larger operand take e^-x of the sum.
+    Rows 0 and 1 pair 710 and 720 with -705 and -700, so their sums (5 to
+    1440) cross all three regions with both factors unusable; the other rows
+    have negative sums and must give NaN."""
+    x = np.array([710.0, 720.0, -705.0, -700.0, 5.0, 8.0])
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(x.size)
+    c = rng.standard_normal(13)
+    z = run(x, y, c)
+    check(x, y, c, z, np.arange(2))
+    assert np.isnan(z[2:]).all()
