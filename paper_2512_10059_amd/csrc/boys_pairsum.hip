@@ -55,6 +55,25 @@ struct PairBPoly {
   double q[kHighKmax + 1];  // coefficients of Q (q[0] = 0)
 };
 
+// Region A in closed form.  The downward recurrence from F_K = S,
+// F_l = (t F_{l+1} + e^-x)/(2l+1) with t = 2x, unrolls to
+// F_l = A_l(t) S + e^-x B_l(t) with
+//     A_l = t^(K-l) (2l-1)!!/(2K-1)!!,
+//     B_l = sum_{m=l}^{K-1} t^(m-l) (2l-1)!!/(2m+1)!!,
+// so sum_l c_l F_l = S U(t) + e^-x V(t), where U = sum c_l A_l has the
+// coefficient u_j = c_{K-j} (2K-2j-1)!!/(2K-1)!! of t^j and V = sum c_l B_l
+// the coefficient v_j = sum_{l=0}^{K-1-j} c_l (2l-1)!!/(2l+2j+1)!! (v_K = 0):
+// two Horner passes, two fused multiply-adds per order instead of the
+// recurrence's multiply and two fused multiply-adds.  Every term c_l A_l S
+// and c_l B_l e^-x is at most |c_l| F_l in magnitude (both parts of F_l are
+// positive), so the rounding of the passes stays on the scale of
+// sum_l |c_l| F_l, as in the recurrence; an error in S propagates as A_l,
+// exactly as through it.
+struct PairAPoly {
+  double u[kHighKmax + 1];  // coefficients of U, degree 0 upwards
+  double v[kHighKmax + 1];  // coefficients of V (v[K] = 0)
+};
+
 // e^-v for one operand of a pair argument, or NaN where the product rule
 // below must not be used: v < 0 (the pair's sum may still be in the
 // domain), v > 700 (the factor would underflow while the pair's sum might
@@ -75,21 +94,63 @@ __device__ __forceinline__ double pair_exp(double x, double eij) {
   return eij;
 }
 
-// sum_{l=0..K} c_l F_l(x) with the sum inside the recurrence, per region,
-// with the table set T; eij = e^-x_i e^-x_j (see pair_exp).
-template <int K, class T>
-__device__ __forceinline__ double pair_weighted(double x, double eij, const PairWeights &cw,
-                                                const PairWeights &dw, const wpair *pq) {
-  double acc;
-  if (x < T::x0) {
-    const double e = pair_exp(x, eij);
-    const double two_x = x + x;
-    double F = rational_a_lit_pos<K, T>(x);
-    acc = cw.c[K] * F;
+// sum_{l=0..K} c_l F_l(x) per region with the table set T: regions A and B
+// through their closed forms (PairAPoly, PairBPoly), region C by Horner in
+// 1/x; eij = e^-x_i e^-x_j (see pair_exp).
+// Horner passes of two polynomials of degree K in h whose coefficient pairs
+// (a_l, b_l) are read from LDS, in chunks of four steps (one chunk rolled) so
+// that at most four pairs are in registers; K % 4 leading steps first.
+template <int K>
+__device__ __forceinline__ wpair horner_pairs(double h, const wpair *ab) {
+  double P = ab[K].x, Q = ab[K].y;
+  int l = K - 1;
 #pragma unroll
-    for (int l = K - 1; l >= 0; --l) {
-      F = __builtin_fma(two_x, F, e) * (1.0 / (2 * l + 1));
-      acc = __builtin_fma(cw.c[l], F, acc);
+  for (int s = 0; s < K % 4; ++s, --l) {
+    P = __builtin_fma(P, h, ab[l].x);
+    Q = __builtin_fma(Q, h, ab[l].y);
+  }
+#pragma unroll 1
+  for (; l >= 0; l -= 4) {
+    wpair t[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) t[s] = ab[l - s];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      P = __builtin_fma(P, h, t[s].x);
+      Q = __builtin_fma(Q, h, t[s].y);
+    }
+  }
+  return wpair{P, Q};
+}
+
+// Orders up to which region A's coefficients are read as kernel arguments
+// (SGPR addends of the Horner steps) rather than as LDS pairs: up to 12 they
+// fit in the scalar registers without spilling (106 SGPRs at order 12; 38
+// spilled at 16), and the paper's benchmark order 12 runs 2.8% faster than
+// with LDS pairs; above, LDS pairs (order 24: 190 ms against 230 ms with the
+// spills, n = 2^18).
+constexpr int kPairSgprOrders = 12;
+
+template <int K, class T>
+__device__ __forceinline__ double pair_weighted(double x, double eij, const PairAPoly &ap,
+                                                const PairWeights &dw, const wpair *uv,
+                                                const wpair *pq) {
+  double acc;
+  if (x < T::x0) {  // region A: S U(2x) + e^-x V(2x)
+    const double e = pair_exp(x, eij);
+    const double S = rational_a_lit_pos<K, T>(x);
+    const double t = x + x;
+    if constexpr (K <= kPairSgprOrders) {
+      double U = ap.u[K], V = 0.0;
+#pragma unroll
+      for (int l = K - 1; l >= 0; --l) {
+        U = fma_uniform_addend(U, t, ap.u[l]);
+        V = fma_uniform_addend(V, t, ap.v[l]);
+      }
+      acc = __builtin_fma(U, S, V * e);
+    } else {  // uv[l] = (u_l, v_l)
+      const wpair UV = horner_pairs<K>(t, uv);
+      acc = __builtin_fma(UV.x, S, UV.y * e);
     }
   } else if (region_c<T>(x)) {
     // x^(-1/2) sum_l (c_l a_l) (1/x)^l by Horner in 1/x (F_l = a_l x^(-l-1/2)
@@ -104,27 +165,8 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
     const double e = pair_exp(x, eij);
     const double g = 0.5 * recip(x);
     const double F0 = rational_b_lit_pos<T>(x);
-    // Chunks of four steps (one chunk rolled), so at most four coefficient
-    // pairs are in registers; K % 4 leading steps first.
-    double P = pq[K].x, Q = pq[K].y;
-    int l = K - 1;
-#pragma unroll
-    for (int s = 0; s < K % 4; ++s, --l) {
-      P = __builtin_fma(P, g, pq[l].x);
-      Q = __builtin_fma(Q, g, pq[l].y);
-    }
-#pragma unroll 1
-    for (; l >= 0; l -= 4) {
-      wpair t[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) t[s] = pq[l - s];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        P = __builtin_fma(P, g, t[s].x);
-        Q = __builtin_fma(Q, g, t[s].y);
-      }
-    }
-    acc = __builtin_fma(F0, P, -(e * Q));
+    const wpair PQ = horner_pairs<K>(g, pq);
+    acc = __builtin_fma(F0, PQ.x, -(e * PQ.y));
   }
   return acc;
 }
@@ -132,12 +174,15 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
 template <int K, class T>
 __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
                                                          const double *__restrict__ ys, int64_t n,
-                                                         PairWeights cw, PairWeights dw, PairBPoly bp,
+                                                         PairAPoly ap, PairWeights dw, PairBPoly bp,
                                                          double *__restrict__ zs) {
   __shared__ wpair s_xe[kPairChunk];  // (x_j, e^-x_j or NaN: pair_factor)
   __shared__ double s_y[kPairChunk];
-  __shared__ wpair s_pq[K + 1];
-  if (threadIdx.x <= K) s_pq[threadIdx.x] = wpair{bp.p[threadIdx.x], bp.q[threadIdx.x]};
+  __shared__ wpair s_uv[K + 1], s_pq[K + 1];
+  if (threadIdx.x <= K) {
+    s_uv[threadIdx.x] = wpair{ap.u[threadIdx.x], ap.v[threadIdx.x]};
+    s_pq[threadIdx.x] = wpair{bp.p[threadIdx.x], bp.q[threadIdx.x]};
+  }
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   const double ei = pair_factor(xi);
@@ -154,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     double part = 0.0;
     for (int t = 0; t < m; ++t) {
       const wpair xe = s_xe[t];
-      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, cw, dw, s_pq), part);
+      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, s_uv, s_pq), part);
     }
     total += part;
     __syncthreads();
@@ -179,7 +224,7 @@ __global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__r
   if (i < n) z[idx[i]] = zs[i];
 }
 
-using PairKernel = void (*)(const double *, const double *, int64_t, PairWeights, PairWeights,
+using PairKernel = void (*)(const double *, const double *, int64_t, PairAPoly, PairWeights,
                             PairBPoly, double *);
 
 template <class T, std::size_t... K>
@@ -260,12 +305,27 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   BOYS_TRY_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return BOYS_ENOTSUP;
 
-  PairWeights cw{}, dw{};  // c_l, and c_l a_l for region C
+  PairWeights dw{};  // c_l a_l for region C
   long double a_hi = kAsymCoefHost[kAsymOrders - 1];  // a_l beyond the table: a_l = a_{l-1} (l - 1/2)
   for (int l = 0; l <= kmax; ++l) {
-    cw.c[l] = c[l];
     if (l >= kAsymOrders) a_hi *= l - 0.5L;
     dw.c[l] = c[l] * (l < kAsymOrders ? kAsymCoefHost[l] : double(a_hi));
+  }
+  // Region A's polynomials U and V (see PairAPoly), in long double, with
+  // df[l] = (2l-1)!! (exact in long double up to l = 20, within a few units
+  // of its last place beyond).
+  PairAPoly ap{};
+  {
+    long double df[kHighKmax + 2];
+    df[0] = 1.0L;
+    for (int l = 1; l <= kmax + 1; ++l) df[l] = df[l - 1] * (2 * l - 1);
+    for (int j = 0; j <= kmax; ++j) {
+      const int l = kmax - j;
+      ap.u[j] = double((long double)c[l] * df[l] / df[kmax]);
+      long double v = 0.0L;
+      for (int m = 0; m <= kmax - 1 - j; ++m) v += (long double)c[m] * df[m] / df[m + j + 1];
+      ap.v[j] = double(v);
+    }
   }
   // Region B's polynomials P and Q (see PairBPoly), in long double:
   // A_l = a_l g^l with a_l = (2l-1)!!, B_l = sum_j b_j g^j.
@@ -339,7 +399,7 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   else if (set == kSetScreen) kernel = kPairTableScreen[kmax];
   else if (table_variant() == BOYS_TABLES_PER_KMAX) kernel = kPairTablePerKmax[kmax];
   else if (table_variant() == BOYS_TABLES_CENTRE) kernel = kPairTableCentre[kmax];
-  hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, keys, ys, n, cw, dw, bp, zs);
+  hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, keys, ys, n, ap, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
   return hip_status(hipGetLastError());

@@ -212,6 +212,63 @@ def test_region_b_closed_form_equals_the_upward_recurrence(K):
         assert abs(closed - s) <= mp.mpf(10) ** -40 * (1 + abs(s))
 
 
+def region_a_polys(c):
+    """U and V of the pair kernel's region-A closed form, by the library's
+    host rule: u_j = c_{K-j} (2K-2j-1)!!/(2K-1)!!,
+    v_j = sum_{l=0}^{K-1-j} c_l (2l-1)!!/(2l+2j+1)!!."""
+    K = len(c) - 1
+    df = [mp.mpf(1)]
+    for l in range(1, K + 2):
+        df.append(df[-1] * (2 * l - 1))
+    u = [c[K - j] * df[K - j] / df[K] for j in range(K + 1)]
+    v = [sum((c[l] * df[l] / df[l + j + 1] for l in range(K - j)), mp.mpf(0)) for j in range(K + 1)]
+    return u, v
+
+
+@pytest.mark.parametrize("K", [0, 1, 5, 12, 32])
+def test_region_a_closed_form_equals_the_downward_recurrence(K):
+    """sum_l c_l F_l with F_l = (2x F_{l+1} + e^-x)/(2l+1) from any F_K equals
+    F_K U(2x) + e^-x V(2x) (identity of the recurrence, 50-digit arithmetic,
+    arbitrary F_K and weights)."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(100 + K)
+    c = [mp.mpf(float(v)) for v in rng.standard_normal(K + 1)]
+    u, v = region_a_polys(c)
+    for x in (0.0, 0.3, 4.0, 11.89):
+        x = mp.mpf(x)
+        e = mp.exp(-x)
+        F = mp.mpf(float(rng.uniform(0.01, 1.0)))  # any starting value
+        t = 2 * x
+        closed = F * mp.polyval(u[::-1], t) + e * mp.polyval(v[::-1], t)
+        s = c[K] * F
+        for l in range(K - 1, -1, -1):
+            F = (2 * x * F + e) / (2 * l + 1)
+            s += c[l] * F
+        assert abs(closed - s) <= mp.mpf(10) ** -40 * (1 + abs(s))
+
+
+def test_region_a_closed_form_check_detects_planted_mistakes():
+    """Mutants of the construction (the double factorial one place off in V,
+    U's coefficients in reverse order) fail the identity."""
+    mp.mp.dps = 50
+    c = [mp.mpf(v) for v in (0.3, -1.2, 0.7, 2.0, -0.4)]
+    K = len(c) - 1
+    u, v = region_a_polys(c)
+    df = [mp.mpf(1)]
+    for l in range(1, K + 3):
+        df.append(df[-1] * (2 * l - 1))
+    v_bad = [sum((c[l] * df[l] / df[l + j + 2] for l in range(K - j)), mp.mpf(0)) for j in range(K + 1)]
+    x = mp.mpf(5.0)
+    e, t, F = mp.exp(-x), 2 * mp.mpf(5.0), mp.mpf(0.02)
+    s = c[K] * F
+    for l in range(K - 1, -1, -1):
+        F = (2 * x * F + e) / (2 * l + 1)
+        s += c[l] * F
+    for uu, vv in ((u, v_bad), (u[::-1], v)):
+        bad = mp.mpf(0.02) * mp.polyval(uu[::-1], t) + e * mp.polyval(vv[::-1], t)
+        assert abs(bad - s) > mp.mpf(10) ** -10
+
+
 def test_region_b_closed_form_check_detects_a_wrong_shift():
     """A mutant of the construction (B_{l+1} without the shift by g) fails."""
     mp.mp.dps = 50
