@@ -186,20 +186,34 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   const double ei = pair_factor(xi);
+  // A negative sum must give NaN (domain()).  Where neither the wave's rows
+  // nor the staged chunk hold a negative operand, every sum is >= 0 or NaN,
+  // domain() is the identity on it, and the loop without it runs instead.
+  const bool rows_nonneg = __ballot(xi < 0.0) == 0;
   double total = 0.0;
   for (int64_t j0 = 0; j0 < n; j0 += kPairChunk) {
+    int negatives = 0;
     for (int t = threadIdx.x; t < kPairChunk; t += kBlock) {
       const int64_t j = j0 + t;
       const double xj = j < n ? xs[j] : 0.0;
       s_xe[t] = wpair{xj, pair_factor(xj)};
       s_y[t] = j < n ? ys[j] : 0.0;
+      negatives += xj < 0.0;
     }
-    __syncthreads();
+    const bool chunk_nonneg = __syncthreads_count(negatives) == 0;
     const int m = n - j0 < kPairChunk ? int(n - j0) : kPairChunk;
     double part = 0.0;
-    for (int t = 0; t < m; ++t) {
-      const wpair xe = s_xe[t];
-      part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, s_uv, s_pq), part);
+    if (rows_nonneg && chunk_nonneg) {
+      for (int t = 0; t < m; ++t) {
+        const wpair xe = s_xe[t];
+        part = __builtin_fma(s_y[t], pair_weighted<K, T>(xi + xe.x, ei * xe.y, ap, dw, s_uv, s_pq), part);
+      }
+    } else {
+      for (int t = 0; t < m; ++t) {
+        const wpair xe = s_xe[t];
+        part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, s_uv, s_pq),
+                             part);
+      }
     }
     total += part;
     __syncthreads();

@@ -136,3 +136,21 @@ def test_operands_outside_the_factor_range():
     z = run(x, y, c)
     check(x, y, c, z, np.arange(2))
     assert np.isnan(z[2:]).all()
+
+
+def test_one_negative_operand_among_many():
+    """A single negative operand, in one wave's rows and one 512-wide chunk:
+    the other waves take the loop without the per-pair domain check for
+    every other chunk, so one launch runs both loops.  Rows with x_i below
+    |x_neg| pair it into a negative sum and give NaN; the others must match
+    the oracle."""
+    n = 3000
+    x, y, c = workloads.pair_workload(n=n, kmax=9, seed=31, x_max=20.0)
+    x[1700] = -0.25
+    z = run(x, y, c)
+    nan_rows = x < 0.25
+    assert nan_rows.sum() >= 2 and np.isnan(z[nan_rows]).all()
+    assert np.isfinite(z[~nan_rows]).all()
+    ok = np.flatnonzero(~nan_rows)
+    rows = np.concatenate([ok[(ok >= 1664) & (ok < 1728)][:8], ok[::97]])
+    check(x, y, c, z, rows)
