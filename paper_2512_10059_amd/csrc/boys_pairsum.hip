@@ -97,28 +97,48 @@ __device__ __forceinline__ double pair_exp(double x, double eij) {
 // sum_{l=0..K} c_l F_l(x) per region with the table set T: regions A and B
 // through their closed forms (PairAPoly, PairBPoly), region C by Horner in
 // 1/x; eij = e^-x_i e^-x_j (see pair_exp).
+// The closed forms' coefficient pairs live in LDS and are read through
+// pointers of this type.
+typedef __attribute__((address_space(3))) const wpair lds_wpair;
+
 // Horner passes of two polynomials of degree K in h whose coefficient pairs
-// (a_l, b_l) are read from LDS, in chunks of four steps (one chunk rolled) so
-// that at most four pairs are in registers; K % 4 leading steps first.
+// (a_l, b_l) are read from LDS, fully unrolled (immediate offsets from one
+// address register), two pairs at a time and double-buffered: the reads of
+// chunk c+1 are issued before the fused multiply-adds of chunk c.  The
+// address passes through an empty asm statement that takes the accumulators
+// after chunk c-1 as inputs, so no read runs further ahead than that: at
+// most four pairs are in registers.  Without it the scheduler issues every
+// read at once (4(K+1) more VGPRs), and with the rolled loop this replaces,
+// each chunk cost three register moves.  The asm also keeps the reads inside
+// the caller's loop, where they would otherwise be hoisted into registers;
+// the pointer's value never changes.
 template <int K>
-__device__ __forceinline__ wpair horner_pairs(double h, const wpair *ab) {
-  double P = ab[K].x, Q = ab[K].y;
-  int l = K - 1;
+__device__ __forceinline__ wpair horner_pairs(double h, lds_wpair *&ab) {
+  constexpr int C = 2;
+  constexpr int kChunks = (K + C - 1) / C;  // chunk c: l = K-1-cC down to K-C-cC
+  const wpair top = ab[K];
+  double P = top.x, Q = top.y;
+  wpair cur[C], nxt[C];
 #pragma unroll
-  for (int s = 0; s < K % 4; ++s, --l) {
-    P = __builtin_fma(P, h, ab[l].x);
-    Q = __builtin_fma(Q, h, ab[l].y);
-  }
-#pragma unroll 1
-  for (; l >= 0; l -= 4) {
-    wpair t[4];
+  for (int s = 0; s < C; ++s)
+    if (K - 1 - s >= 0) cur[s] = ab[K - 1 - s];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) t[s] = ab[l - s];
+  for (int c = 0; c < kChunks; ++c) {
+    const int l0 = K - 1 - c * C;
+    if (c + 1 < kChunks) {
+      asm volatile("" : "+v"(ab) : "v"(P), "v"(Q));
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      P = __builtin_fma(P, h, t[s].x);
-      Q = __builtin_fma(Q, h, t[s].y);
+      for (int s = 0; s < C; ++s)
+        if (l0 - C - s >= 0) nxt[s] = ab[l0 - C - s];
     }
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+      if (l0 - s >= 0) {
+        P = __builtin_fma(P, h, cur[s].x);
+        Q = __builtin_fma(Q, h, cur[s].y);
+      }
+#pragma unroll
+    for (int s = 0; s < C; ++s) cur[s] = nxt[s];
   }
   return wpair{P, Q};
 }
@@ -133,24 +153,30 @@ constexpr int kPairSgprOrders = 12;
 
 template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, double eij, const PairAPoly &ap,
-                                                const PairWeights &dw, const wpair *uv,
-                                                const wpair *pq) {
+                                                const PairWeights &dw, lds_wpair *&uv,
+                                                lds_wpair *&pq) {
   double acc;
   if (x < T::x0) {  // region A: S U(2x) + e^-x V(2x)
-    const double e = pair_exp(x, eij);
+    // e^-x is taken where it is used: formed before the branches, the
+    // fallback's -x became a register that the reciprocals then read instead
+    // of negating their operand (two more instructions per pair).
     const double S = rational_a_lit_pos<K, T>(x);
     const double t = x + x;
     if constexpr (K <= kPairSgprOrders) {
-      double U = ap.u[K], V = 0.0;
+      double U = ap.u[K];
 #pragma unroll
-      for (int l = K - 1; l >= 0; --l) {
-        U = fma_uniform_addend(U, t, ap.u[l]);
-        V = fma_uniform_addend(V, t, ap.v[l]);
+      for (int l = K - 1; l >= 0; --l) U = fma_uniform_addend(U, t, ap.u[l]);
+      if constexpr (K == 0) {
+        acc = U * S;
+      } else {  // V has degree K - 1 (v_K = 0)
+        double V = ap.v[K - 1];
+#pragma unroll
+        for (int l = K - 2; l >= 0; --l) V = fma_uniform_addend(V, t, ap.v[l]);
+        acc = __builtin_fma(U, S, V * pair_exp(x, eij));
       }
-      acc = __builtin_fma(U, S, V * e);
     } else {  // uv[l] = (u_l, v_l)
       const wpair UV = horner_pairs<K>(t, uv);
-      acc = __builtin_fma(UV.x, S, UV.y * e);
+      acc = __builtin_fma(UV.x, S, UV.y * pair_exp(x, eij));
     }
   } else if (region_c<T>(x)) {
     // x^(-1/2) sum_l (c_l a_l) (1/x)^l by Horner in 1/x (F_l = a_l x^(-l-1/2)
@@ -162,27 +188,36 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
     for (int l = K - 1; l >= 0; --l) P = fma_uniform_addend(P, g, dw.c[l]);
     acc = P * r;
   } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l)
-    const double e = pair_exp(x, eij);
     const double g = 0.5 * recip(x);
     const double F0 = rational_b_lit_pos<T>(x);
     const wpair PQ = horner_pairs<K>(g, pq);
-    acc = __builtin_fma(F0, PQ.x, -(e * PQ.y));
+    acc = __builtin_fma(F0, PQ.x, -(pair_exp(x, eij) * PQ.y));
   }
   return acc;
 }
+
+// One staged column j in LDS: (x_j, e^-x_j or NaN: pair_factor) and
+// (y_j, unused), so one address register serves both reads of a pair.
+struct alignas(32) PairCol {
+  wpair xe;
+  wpair y;
+};
 
 template <int K, class T>
 __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restrict__ xs,
                                                          const double *__restrict__ ys, int64_t n,
                                                          PairAPoly ap, PairWeights dw, PairBPoly bp,
                                                          double *__restrict__ zs) {
-  __shared__ wpair s_xe[kPairChunk];  // (x_j, e^-x_j or NaN: pair_factor)
-  __shared__ double s_y[kPairChunk];
+  __shared__ PairCol s_col[kPairChunk];
   __shared__ wpair s_uv[K + 1], s_pq[K + 1];
   if (threadIdx.x <= K) {
     s_uv[threadIdx.x] = wpair{ap.u[threadIdx.x], ap.v[threadIdx.x]};
     s_pq[threadIdx.x] = wpair{bp.p[threadIdx.x], bp.q[threadIdx.x]};
   }
+  // Passed through an empty asm statement every pair (and inside
+  // horner_pairs), so their reads are not hoisted out of the pair loop.
+  lds_wpair *uv = (lds_wpair *)s_uv;
+  lds_wpair *pq = (lds_wpair *)s_pq;
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   const double ei = pair_factor(xi);
@@ -196,8 +231,8 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     for (int t = threadIdx.x; t < kPairChunk; t += kBlock) {
       const int64_t j = j0 + t;
       const double xj = j < n ? xs[j] : 0.0;
-      s_xe[t] = wpair{xj, pair_factor(xj)};
-      s_y[t] = j < n ? ys[j] : 0.0;
+      s_col[t].xe = wpair{xj, pair_factor(xj)};
+      s_col[t].y = wpair{j < n ? ys[j] : 0.0, 0.0};
       negatives += xj < 0.0;
     }
     const bool chunk_nonneg = __syncthreads_count(negatives) == 0;
@@ -205,14 +240,17 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
     double part = 0.0;
     if (rows_nonneg && chunk_nonneg) {
       for (int t = 0; t < m; ++t) {
-        const wpair xe = s_xe[t];
-        part = __builtin_fma(s_y[t], pair_weighted<K, T>(xi + xe.x, ei * xe.y, ap, dw, s_uv, s_pq), part);
+        asm volatile("" : "+v"(uv), "+v"(pq));
+        const wpair xe = s_col[t].xe;
+        const double y = s_col[t].y.x;
+        part = __builtin_fma(y, pair_weighted<K, T>(xi + xe.x, ei * xe.y, ap, dw, uv, pq), part);
       }
     } else {
       for (int t = 0; t < m; ++t) {
-        const wpair xe = s_xe[t];
-        part = __builtin_fma(s_y[t], pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, s_uv, s_pq),
-                             part);
+        asm volatile("" : "+v"(uv), "+v"(pq));
+        const wpair xe = s_col[t].xe;
+        const double y = s_col[t].y.x;
+        part = __builtin_fma(y, pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, uv, pq), part);
       }
     }
     total += part;
