@@ -278,10 +278,13 @@ __device__ __forceinline__ double rational_a_lit_pos(double x) {
 }
 
 // r_B of a table set with div_positive for the quotient (literal
-// coefficients, SGPR addends, as rational_b_t).
+// coefficients, SGPR addends, as rational_b_t).  A caller in a loop may pass
+// the numerator's leading coefficient held in a VGPR: the first Horner step
+// has it as its multiplicand, which the literal form moves into VGPRs (two
+// moves) on every call.
 template <class T>
-__device__ __forceinline__ double rational_b_lit_pos(double x) {
-  double p = rb_p_at<T>(T::rb_n);
+__device__ __forceinline__ double rational_b_lit_pos(double x, double top = rb_p_at<T>(T::rb_n)) {
+  double p = top;
 #pragma unroll
   for (int i = T::rb_n - 1; i >= 0; --i) p = fma_uniform_addend(p, x, rb_p_at<T>(i));
   if constexpr (T::rb_m == 0) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -50,9 +51,13 @@ struct PairWeights {
 // (prod (n+1/2)/x <= 1), so |c_l A_l F_0| and |c_l e B_l| stay below
 // |c_l| F_0: the absolute rounding stays on the scale of the recurrence's,
 // and an error in F_0 propagates as A_l, exactly as through the recurrence.
+// The kernel runs both passes in h = 1/x = 2g: the coefficient of g^l is
+// stored times 2^-l, so every Horner step is the step in g times a power of
+// two, which rounds identically (bit for bit, short of underflow), and the
+// multiply forming g is saved.
 struct PairBPoly {
-  double p[kHighKmax + 1];  // coefficients of P, degree 0 upwards
-  double q[kHighKmax + 1];  // coefficients of Q (q[0] = 0)
+  double p[kHighKmax + 1];  // coefficients of P(h/2) in h, degree 0 upwards
+  double q[kHighKmax + 1];  // coefficients of Q(h/2) (q[0] = 0)
 };
 
 // Region A in closed form.  The downward recurrence from F_K = S,
@@ -69,9 +74,11 @@ struct PairBPoly {
 // positive), so the rounding of the passes stays on the scale of
 // sum_l |c_l| F_l, as in the recurrence; an error in S propagates as A_l,
 // exactly as through it.
+// As in region B, the passes run in x itself: the coefficient of t^j is
+// stored times 2^j (exact), which saves forming t.
 struct PairAPoly {
-  double u[kHighKmax + 1];  // coefficients of U, degree 0 upwards
-  double v[kHighKmax + 1];  // coefficients of V (v[K] = 0)
+  double u[kHighKmax + 1];  // coefficients of U(2x) in x, degree 0 upwards
+  double v[kHighKmax + 1];  // coefficients of V(2x) (v[K] = 0)
 };
 
 // e^-v for one operand of a pair argument, or NaN where the product rule
@@ -154,28 +161,27 @@ constexpr int kPairSgprOrders = 12;
 template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, double eij, const PairAPoly &ap,
                                                 const PairWeights &dw, lds_wpair *&uv,
-                                                lds_wpair *&pq) {
+                                                lds_wpair *&pq, double rb_top) {
   double acc;
   if (x < T::x0) {  // region A: S U(2x) + e^-x V(2x)
     // e^-x is taken where it is used: formed before the branches, the
     // fallback's -x became a register that the reciprocals then read instead
     // of negating their operand (two more instructions per pair).
     const double S = rational_a_lit_pos<K, T>(x);
-    const double t = x + x;
     if constexpr (K <= kPairSgprOrders) {
       double U = ap.u[K];
 #pragma unroll
-      for (int l = K - 1; l >= 0; --l) U = fma_uniform_addend(U, t, ap.u[l]);
+      for (int l = K - 1; l >= 0; --l) U = fma_uniform_addend(U, x, ap.u[l]);
       if constexpr (K == 0) {
         acc = U * S;
       } else {  // V has degree K - 1 (v_K = 0)
         double V = ap.v[K - 1];
 #pragma unroll
-        for (int l = K - 2; l >= 0; --l) V = fma_uniform_addend(V, t, ap.v[l]);
+        for (int l = K - 2; l >= 0; --l) V = fma_uniform_addend(V, x, ap.v[l]);
         acc = __builtin_fma(U, S, V * pair_exp(x, eij));
       }
     } else {  // uv[l] = (u_l, v_l)
-      const wpair UV = horner_pairs<K>(t, uv);
+      const wpair UV = horner_pairs<K>(x, uv);
       acc = __builtin_fma(UV.x, S, UV.y * pair_exp(x, eij));
     }
   } else if (region_c<T>(x)) {
@@ -187,10 +193,10 @@ __device__ __forceinline__ double pair_weighted(double x, double eij, const Pair
 #pragma unroll
     for (int l = K - 1; l >= 0; --l) P = fma_uniform_addend(P, g, dw.c[l]);
     acc = P * r;
-  } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l)
-    const double g = 0.5 * recip(x);
-    const double F0 = rational_b_lit_pos<T>(x);
-    const wpair PQ = horner_pairs<K>(g, pq);
+  } else {  // region B (and NaN): F_0 P(g) - e^-x Q(g), pq[l] = (p_l, q_l) in h = 2g
+    const double h = recip(x);
+    const double F0 = rational_b_lit_pos<T>(x, rb_top);
+    const wpair PQ = horner_pairs<K>(h, pq);
     acc = __builtin_fma(F0, PQ.x, -(pair_exp(x, eij) * PQ.y));
   }
   return acc;
@@ -218,6 +224,9 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
   // horner_pairs), so their reads are not hoisted out of the pair loop.
   lds_wpair *uv = (lds_wpair *)s_uv;
   lds_wpair *pq = (lds_wpair *)s_pq;
+  // r_B's leading numerator coefficient, kept in a VGPR across the loop.
+  double rb_top = rb_p_at<T>(T::rb_n);
+  asm volatile("" : "+v"(rb_top));
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const double xi = i < n ? xs[i] : 0.0;
   const double ei = pair_factor(xi);
@@ -243,14 +252,15 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
         asm volatile("" : "+v"(uv), "+v"(pq));
         const wpair xe = s_col[t].xe;
         const double y = s_col[t].y.x;
-        part = __builtin_fma(y, pair_weighted<K, T>(xi + xe.x, ei * xe.y, ap, dw, uv, pq), part);
+        part = __builtin_fma(y, pair_weighted<K, T>(xi + xe.x, ei * xe.y, ap, dw, uv, pq, rb_top), part);
       }
     } else {
       for (int t = 0; t < m; ++t) {
         asm volatile("" : "+v"(uv), "+v"(pq));
         const wpair xe = s_col[t].xe;
         const double y = s_col[t].y.x;
-        part = __builtin_fma(y, pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, uv, pq), part);
+        part = __builtin_fma(
+            y, pair_weighted<K, T>(domain(xi + xe.x), ei * xe.y, ap, dw, uv, pq, rb_top), part);
       }
     }
     total += part;
@@ -365,7 +375,7 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
   }
   // Region A's polynomials U and V (see PairAPoly), in long double, with
   // df[l] = (2l-1)!! (exact in long double up to l = 20, within a few units
-  // of its last place beyond).
+  // of its last place beyond); rounded to double, then scaled by 2^j.
   PairAPoly ap{};
   {
     long double df[kHighKmax + 2];
@@ -373,14 +383,15 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
     for (int l = 1; l <= kmax + 1; ++l) df[l] = df[l - 1] * (2 * l - 1);
     for (int j = 0; j <= kmax; ++j) {
       const int l = kmax - j;
-      ap.u[j] = double((long double)c[l] * df[l] / df[kmax]);
+      ap.u[j] = std::ldexp(double((long double)c[l] * df[l] / df[kmax]), j);
       long double v = 0.0L;
       for (int m = 0; m <= kmax - 1 - j; ++m) v += (long double)c[m] * df[m] / df[m + j + 1];
-      ap.v[j] = double(v);
+      ap.v[j] = std::ldexp(double(v), j);
     }
   }
   // Region B's polynomials P and Q (see PairBPoly), in long double:
-  // A_l = a_l g^l with a_l = (2l-1)!!, B_l = sum_j b_j g^j.
+  // A_l = a_l g^l with a_l = (2l-1)!!, B_l = sum_j b_j g^j; rounded to
+  // double, then scaled by 2^-l.
   PairBPoly bp{};
   {
     long double a = 1.0L, b[kHighKmax + 2] = {}, pq_p[kHighKmax + 1] = {}, pq_q[kHighKmax + 1] = {};
@@ -393,8 +404,8 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
       a *= 2 * l + 1;
     }
     for (int l = 0; l <= kmax; ++l) {
-      bp.p[l] = double(pq_p[l]);
-      bp.q[l] = double(pq_q[l]);
+      bp.p[l] = std::ldexp(double(pq_p[l]), -l);
+      bp.q[l] = std::ldexp(double(pq_q[l]), -l);
     }
   }
 
