@@ -355,12 +355,12 @@ __device__ __forceinline__ double batch_rational_a(double x, int k) {
 }
 
 template <class T>
-__device__ __forceinline__ double batch_rational_b(double x, int k) {
+__device__ __forceinline__ double batch_rational_b(double x, int k, double top) {
   if constexpr (kPerKmaxRows<T>) {
     return order_dispatch(
         k, [x](auto K) { return rational_b_lit_pos<PerKmaxTables<decltype(K)::value>>(x); });
   } else {
-    return rational_b_lit_pos<T>(x);
+    return rational_b_lit_pos<T>(x, top);
   }
 }
 
@@ -430,51 +430,90 @@ __device__ __forceinline__ double fma_step(double h, double t, double c) {
   return r;
 }
 
-// Region A.  ta[kSweepPadA + s] = (w_s (2s-1)!!/(2k-1)!!, (2k-1)!!/(2s-1)!!)
-// for 1 <= s <= k, (w_0/(2k-1)!!, 0) for s = 0, zeros for s < 0.
+// Both sweeps take their first chunk apart from the loop: from z = v = 0
+// the first step leaves z = a and v = 0 (exactly, for finite x) and the
+// second adds v = z b by a multiply, which drops the two zeroing moves and
+// two fused multiply-adds per argument.  Padding entries make the first
+// chunk whole at every k.
+
+// Region A.  The tables hold the entries scaled by powers of two so that
+// the sweep multiplies by x instead of 2x (saving the add that formed 2x):
+// ta[kSweepPadA + s] = 2^(k-s) w_s (2s-1)!!/(2k-1)!!, 2^(s-k-1) (2k-1)!!/(2s-1)!!)
+// for 1 <= s <= k, (2^k w_0/(2k-1)!!, 0) for s = 0, zeros for s < 0.  After
+// entry s the state is (2^(k-s) z_s, v_s) of the unscaled sweep in 2x, since
+// scaling by a power of two commutes with rounding: the same result, bit for
+// bit (short of underflow, which the entries' sizes rule out).
 template <int CH, class T = PaperTables>
 __device__ __forceinline__ double wsum_sweep_a(double x, int k, const wpair *ta) {
+  static_assert(CH >= 2, "the peeled first chunk has two steps or more");
   const double e = exp_neg(x);
   const double S = batch_rational_a<T>(x, k);
-  const double two_x = x + x;
   const int steps = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
   const wpair *t = ta + (kSweepPadA + k + 1 - steps);
-  double z = 0.0, v = 0.0;
-  for (int c0 = 0; c0 < steps; c0 += CH) {
-    wpair q[CH];
+  wpair q[CH];
+#pragma unroll
+  for (int s = 0; s < CH; ++s) q[s] = t[s];
+  double z = q[0].x;
+  double v = z * q[1].y;
+  z = fma_step(x, z, q[1].x);
+#pragma unroll
+  for (int s = 2; s < CH; ++s) {  // z first: neither step reads the other's result
+    const double zs = z;
+    z = fma_step(x, zs, q[s].x);
+    v = fma_step(zs, q[s].y, v);
+  }
+  for (int c0 = CH; c0 < steps; c0 += CH) {
 #pragma unroll
     for (int s = 0; s < CH; ++s) q[s] = t[c0 + s];
 #pragma unroll
-    for (int s = 0; s < CH; ++s) {  // z first: neither step reads the other's result
+    for (int s = 0; s < CH; ++s) {
       const double zs = z;
-      z = fma_step(two_x, zs, q[s].x);
+      z = fma_step(x, zs, q[s].x);
       v = fma_step(zs, q[s].y, v);
     }
   }
   return __builtin_fma(z, S, v * e);
 }
 
-// Region B.  tb[l-1] = (w_{l-1} (2l-3)!!, -1/(2l-1)!!) for 1 <= l <= k,
-// (w_k (2k-1)!!, 0) for l = k+1, zeros above.
+// Region B.  Unscaled, tb[l-1] = (w_{l-1} (2l-3)!!, -1/(2l-1)!!) for
+// 1 <= l <= k, (w_k (2k-1)!!, 0) for l = k+1, zeros above, swept in
+// g = 1/(2x).  The tables hold entry i = l-1 as (2^-i a_i, 2^i b_i) and the
+// sweep multiplies by h = 1/x = 2g: after entry i the state is
+// (2^-i z_i, v_i / 2) of the unscaled sweep, so z comes out unchanged and
+// h (v/2) = g v, bit for bit, and the multiply that formed g is saved.
+// top_b is r_B's leading numerator coefficient (see rational_b_lit_pos);
+// the per-kmax set ignores it.
 template <int CH, class T = PaperTables>
-__device__ __forceinline__ double wsum_sweep_b(double x, int k, const wpair *tb) {
+__device__ __forceinline__ double wsum_sweep_b(double x, int k, const wpair *tb, double top_b) {
+  static_assert(CH >= 2, "the peeled first chunk has two steps or more");
   const double e = exp_neg(x);
-  const double g = 0.5 * recip(x);
-  const double S = batch_rational_b<T>(x, k);
+  const double h = recip(x);
+  const double S = batch_rational_b<T>(x, k, top_b);
   const int top = (k + CH) & ~(CH - 1);  // k + 1 rounded up to whole chunks
-  double z = 0.0, v = 0.0;
-  for (int l0 = top; l0 > 0; l0 -= CH) {
-    wpair q[CH];
+  wpair q[CH];
+  const wpair *b0 = tb + (top - CH);  // one base, non-negative offsets
+#pragma unroll
+  for (int s = 0; s < CH; ++s) q[s] = b0[CH - 1 - s];
+  double z = q[0].x;
+  double v = z * q[1].y;
+  z = fma_step(h, z, q[1].x);
+#pragma unroll
+  for (int s = 2; s < CH; ++s) {  // z first: neither step reads the other's result
+    const double zs = z;
+    z = fma_step(h, zs, q[s].x);
+    v = fma_step(zs, q[s].y, v);
+  }
+  for (int l0 = top - CH; l0 > 0; l0 -= CH) {
 #pragma unroll
     for (int s = 0; s < CH; ++s) q[s] = tb[l0 - 1 - s];
 #pragma unroll
-    for (int s = 0; s < CH; ++s) {  // z first: neither step reads the other's result
+    for (int s = 0; s < CH; ++s) {
       const double zs = z;
-      z = fma_step(g, zs, q[s].x);
+      z = fma_step(h, zs, q[s].x);
       v = fma_step(zs, q[s].y, v);
     }
   }
-  return __builtin_fma(z, S, (g * v) * e);
+  return __builtin_fma(z, S, (h * v) * e);
 }
 
 // Region C: x^(-1/2) P(1/x) with P(g) = sum_l d_l g^l, d_l = w_l a_l.  The

@@ -234,12 +234,14 @@ __device__ __forceinline__ BatchFields load_batch(const WsArgs &a, int32_t b) {
 // Forms the wave's LDS tables for a batch of order k with weights w (see the
 // weight sweeps in boys_device_f64_batched.hpp), one entry per lane; with
 // D_l = (2l-1)!!:
-//   ta[8 + s] = (w_s D_s / D_k, D_k / D_s)  1 <= s <= k;  (w_0 / D_k, 0) at s = 0;
-//   tb[l - 1] = (w_{l-1} (2l-3)!!, -1/(2l-1)!!)  1 <= l <= k;
-//               (w_k (2k-1)!!, 0) at l = k+1;
+//   ta[8 + s] = (2^(k-s) w_s D_s / D_k, 2^(s-k-1) D_k / D_s)  1 <= s <= k;
+//               (2^k w_0 / D_k, 0) at s = 0;
+//   tb[i]     = (2^-i w_i (2i-1)!!, -2^i / (2i+1)!!)  0 <= i < k;
+//               (2^-k w_k (2k-1)!!, 0) at i = k;
 //   tc[l]     = w_l a_l  l <= k  (region C);
-// zeros elsewhere.  The weight loads use indices clamped into the batch's
-// range, so they are unconditional and in flight together.
+// zeros elsewhere (the powers of two let the sweeps run in x and 1/x).  The
+// weight loads use indices clamped into the batch's range, so they are
+// unconditional and in flight together.
 __device__ __forceinline__ void load_tables(const double *w, int k, int lane, wpair *ta, wpair *tb,
                                             double *tc) {
   // Every load is unconditional, from an index clamped into its table; the
@@ -253,8 +255,10 @@ __device__ __forceinline__ void load_tables(const double *w, int k, int lane, wp
   const double al = kAsymCoef[lc];
   const double dk = kDFact[k], idk = kInvDFact[k];
   const bool in_a = s >= 0 && s <= k, in_b = lane <= k;
-  const wpair ea{in_a ? ws * (dfs * idk) : 0.0, in_a && s >= 1 ? ids * dk : 0.0};
-  const wpair eb{in_b ? wl * dfl : 0.0, lane + 1 <= k ? -idp : 0.0};
+  const wpair ea{__builtin_amdgcn_ldexp(in_a ? ws * (dfs * idk) : 0.0, k - s),
+                 __builtin_amdgcn_ldexp(in_a && s >= 1 ? ids * dk : 0.0, s - k - 1)};
+  const wpair eb{__builtin_amdgcn_ldexp(in_b ? wl * dfl : 0.0, -lane),
+                 __builtin_amdgcn_ldexp(lane + 1 <= k ? -idp : 0.0, lane)};
   const double ec = in_b ? wl * al : 0.0;
   if (lane < kSweepLenA) ta[lane] = ea;
   if (lane < kSweepLenB) tb[lane] = eb;
@@ -354,6 +358,13 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
   }
   bool reload = true;
   double xn[ITEMS];        // PF: the next tile's arguments
+  // r_B's leading numerator coefficient in a VGPR for the whole kernel
+  // instead of two literal moves per region-B pass (fixed-region sets).
+  double top_b = 0.0;
+  if constexpr (!kPerKmaxRows<TS>) {
+    top_b = rb_p_at<TS>(TS::rb_n);
+    asm volatile("" : "+v"(top_b));
+  }
   bool have_next = false;  // PF: xn holds the tile this iteration takes
 
   for (;;) {
@@ -489,7 +500,7 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
           double acc;
           if (q < nA) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
           else if (q < nAC) acc = wsum_region_c(xq, k, tc);
-          else acc = wsum_sweep_b<CH, TS>(xq, k, tb);
+          else acc = wsum_sweep_b<CH, TS>(xq, k, tb, top_b);
           s_x[wv][q] = acc;
         }
       }
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
           double acc;
           if (xq < x0v) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
           else if (xq > x1v) acc = wsum_region_c(xq, k, tc);
-          else acc = wsum_sweep_b<CH, TS>(xq, k, tb);
+          else acc = wsum_sweep_b<CH, TS>(xq, k, tb, top_b);
           a.out[first + p] = acc;
         }
       }

@@ -19,7 +19,9 @@ Pins, none of which reuses the generator's arithmetic:
   and operation order, emulated in FP64 with exact fused multiply-adds) give
   sum_l w_l F_l to within their rounding bound for every order 0..32, with the
   exact F_l from mpmath's incomplete gamma and the exact seed and e^-x, so a
-  mistake in the algebra shows as an O(1) error; planted mistakes fail."""
+  mistake in the algebra shows as an O(1) error; planted mistakes fail; and
+  the kernel's power-of-two-scaled, first-step-peeled form gives the same
+  doubles as the plain recurrence."""
 import math
 import os
 import re
@@ -312,43 +314,35 @@ def rnd(q):
     return float(q)
 
 
-def sweep_a(x, w, S, e, CH=4, mistake=None):
-    """Region A as the kernel runs it: table entries (w_s D_s/D_k, D_k/D_s),
-    (w_0/D_k, 0) at s = 0, zeros below, swept upwards in whole chunks from
-    below, z first, then sum = z S + v e."""
+def sweep_entries_a(x, w, CH, mistake=None):
+    """Region A's table entries (w_s D_s/D_k, D_k/D_s), (w_0/D_k, 0) at s = 0,
+    zeros below, in the order the sweep takes them (upwards, padded below to
+    whole chunks)."""
     k = len(w) - 1
     D, ID = C["dfact"], C["inv_dfact"]
     dk, idk = D[k], ID[k]
-    ent = {}
-    for s in range(k + 1):
+    out = []
+    steps = (k + CH) & ~(CH - 1)
+    for s in range(k + 1 - steps, k + 1):
+        if s < 0:
+            out.append((s, 0.0, 0.0))
+            continue
         a = rnd(Fraction(w[s]) * Fraction(rnd(Fraction(D[s]) * Fraction(idk))))
         b = rnd(Fraction(ID[s]) * Fraction(dk)) if s >= 1 else 0.0
         if mistake == "no_scale":
             a = rnd(Fraction(w[s]) * Fraction(D[s]))
-        ent[s] = (a, b)
-    steps = (k + CH) & ~(CH - 1)
-    two_x = x + x
-    z = v = 0.0
-    for s in range(k + 1 - steps, k + 1):
-        a, b = ent.get(s, (0.0, 0.0))
-        if mistake == "new_z":
-            z = fma(two_x, z, a)
-            v = fma(z, b, v)
-        else:
-            z, v = fma(two_x, z, a), fma(z, b, v)
-    return fma(z, S, rnd(Fraction(v) * Fraction(e)))
+        out.append((s, a, b))
+    return out
 
 
-def sweep_b(x, w, S, e, CH=4, mistake=None):
-    """Region B as the kernel runs it: table entries l = 1..top,
-    (w_{l-1} D_{l-1}, -1/D_l) for l <= k, (w_k D_k, 0) at l = k+1, zeros
-    above, swept downwards in whole chunks from above, z first, then
-    sum = z S + (g v) e with g = 1/(2x)."""
+def sweep_entries_b(w, CH, mistake=None):
+    """Region B's entries i = l-1: (w_i D_i, -1/D_{i+1}) for i < k,
+    (w_k D_k, 0) at i = k, zeros above, in the sweep's order (downwards from
+    the top of the padded range)."""
     k = len(w) - 1
     D, ID = C["dfact"], C["inv_dfact"]
     top = (k + CH) & ~(CH - 1)
-    g = rnd(Fraction(1) / (2 * Fraction(x)))
-    z = v = 0.0
+    out = []
     for l in range(top, 0, -1):
         a = rnd(Fraction(w[l - 1]) * Fraction(D[l - 1])) if l - 1 <= k else 0.0
         b = -ID[l] if l <= k else 0.0
@@ -356,8 +350,67 @@ def sweep_b(x, w, S, e, CH=4, mistake=None):
             b = -b
         if mistake == "shift":
             a = rnd(Fraction(w[l]) * Fraction(D[l])) if 1 <= l <= k else 0.0
-        z, v = fma(g, z, a), fma(z, b, v)
-    return fma(z, S, rnd(Fraction(rnd(Fraction(g) * Fraction(v))) * Fraction(e)))
+        out.append((l - 1, a, b))
+    return out
+
+
+def sweep_plain(mult, entries, mistake=None):
+    """The sweeps' recurrence from z = v = 0: z <- mult z + a, v <- v + z_prev b."""
+    z = v = 0.0
+    for _, a, b in entries:
+        if mistake == "new_z":
+            z = fma(mult, z, a)
+            v = fma(z, b, v)
+        else:
+            z, v = fma(mult, z, a), fma(z, b, v)
+    return z, v
+
+
+def sweep_kernel(mult, entries, mistake=None):
+    """As the kernel runs it: the first step leaves z = a_0 (v stays 0), the
+    second forms v by a multiply, the rest are fused multiply-adds."""
+    (_, a0, _), (_, a1, b1) = entries[0], entries[1]
+    z = a0
+    v = z * b1
+    z = fma(mult, z, a1)
+    for _, a, b in entries[2:]:
+        if mistake == "new_z":
+            z = fma(mult, z, a)
+            v = fma(z, b, v)
+        else:
+            z, v = fma(mult, z, a), fma(z, b, v)
+    return z, v
+
+
+def sweep_a(x, w, S, e, CH=4, mistake=None, kernel=True):
+    """Region A, sum = z S + v e.  The kernel's tables hold entry s as
+    (2^(k-s) a_s, 2^(s-k-1) b_s) and it sweeps in x; kernel=False runs the
+    unscaled entries in 2x from z = v = 0."""
+    k = len(w) - 1
+    ent = sweep_entries_a(x, w, CH, mistake)
+    if kernel:
+        scaled = [(s, math.ldexp(a, k - s), math.ldexp(b, s - k - 1)) for s, a, b in ent]
+        z, v = sweep_kernel(x, scaled, mistake)
+    else:
+        z, v = sweep_plain(x + x, ent, mistake)
+    return fma(z, S, rnd(Fraction(v) * Fraction(e)))
+
+
+def sweep_b(x, w, S, e, CH=4, mistake=None, kernel=True):
+    """Region B, sum = z S + (g v) e with g = 1/(2x).  The kernel's tables hold
+    entry i as (2^-i a_i, 2^i b_i) and it sweeps in h = 1/x, ending with
+    (h v) e; kernel=False runs the unscaled entries in g from z = v = 0."""
+    ent = sweep_entries_b(w, CH, mistake)
+    if kernel:
+        h = rnd(Fraction(1) / Fraction(x))
+        scaled = [(i, math.ldexp(a, -i), math.ldexp(b, i)) for i, a, b in ent]
+        z, v = sweep_kernel(h, scaled, mistake)
+        m = h
+    else:
+        g = rnd(Fraction(1) / (2 * Fraction(x)))
+        z, v = sweep_plain(g, ent, mistake)
+        m = g
+    return fma(z, S, rnd(Fraction(rnd(Fraction(m) * Fraction(v))) * Fraction(e)))
 
 
 def exact_F(x, K):
@@ -404,3 +457,18 @@ def test_weight_sweeps_reproduce_the_weighted_sum(CH):
 def test_weight_sweep_check_detects_planted_mistakes(mistake):
     with pytest.raises(AssertionError):
         check_sweeps(mistake=mistake)
+
+
+@pytest.mark.parametrize("CH", [4, 8])
+def test_scaled_peeled_sweeps_round_like_the_plain_recurrence(CH):
+    """The kernel's form (power-of-two-scaled entries swept in x or 1/x, the
+    first step taken as z = a_0 and the second's v formed by a multiply)
+    gives the same double as the plain sweep in 2x or 1/(2x) from z = v = 0,
+    for every case and order: scaling by a power of two commutes with
+    rounding, and the first steps are exact."""
+    rng = np.random.default_rng(8)
+    for K, x, region in sweep_cases():
+        w = [float(v) for v in rng.standard_normal(K + 1)]
+        S, e = float(rng.uniform(0.1, 1.0)), float(rng.uniform(1e-13, 1.0))
+        f = sweep_a if region == "A" else sweep_b
+        assert f(x, w, S, e, CH) == f(x, w, S, e, CH, kernel=False), (K, x, region)
