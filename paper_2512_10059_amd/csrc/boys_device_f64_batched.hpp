@@ -61,14 +61,18 @@ constexpr double kExpTaylor[kExpDegree + 1] = BOYS_EXP_TAYLOR_INIT;
 // one SGPR operand, instead of a fused multiply-add with two constants, one
 // of which would first be moved into VGPRs; its extra rounding is on a term
 // below 2^-52 of the result.
+//
+// -n is formed directly as rint(-x/ln2) (rounding to nearest even is
+// symmetric, so this is exactly -rint(x/ln2)) and n enters the reduction
+// through negated operands, which saves the integer negation of the scale.
 __device__ __forceinline__ double exp_neg(double x) {
-  const double nd = __builtin_rint(x * kExpInvLn2);
-  double r = __builtin_fma(nd, kExpLn2Hi, -x);
-  r = __builtin_fma(nd, kExpLn2Lo, r);
+  const double mn = __builtin_rint(-x * kExpInvLn2);  // -n
+  double r = __builtin_fma(-mn, kExpLn2Hi, -x);
+  r = __builtin_fma(-mn, kExpLn2Lo, r);
   double p = add_uniform(r * kExpTaylor[kExpDegree], kExpTaylor[kExpDegree - 1]);
 #pragma unroll
   for (int j = kExpDegree - 2; j >= 0; --j) p = fma_uniform_addend(p, r, kExpTaylor[j]);
-  return __builtin_amdgcn_ldexp(p, -int(nd));
+  return __builtin_amdgcn_ldexp(p, int(mn));
 }
 
 // 1/x for finite x in the normal range: the hardware reciprocal refined by

@@ -492,17 +492,23 @@ __global__ __launch_bounds__(kWsBlock) void ws_kernel(WsArgs a) {
       else bin(std::false_type{});
       const int nAC = nA + nC;
       wave_sync();
+      // The passes cover the items holding a valid slot.  In the last one of
+      // a partial tile, lanes past the tile's end (slots from count on,
+      // after every class) evaluate their stale slot on region B's path and
+      // write it back, where no store reads it: those lanes were masked off
+      // in the same wave instructions before, so they cost nothing, and each
+      // pass saves the bounds compare and its exec-mask updates.  The paths
+      // touch no memory that depends on the argument.
+      const int passes = (count + 63) >> 6;
 #pragma unroll 1
-      for (int it = 0; it < ITEMS; ++it) {
+      for (int it = 0; it < passes; ++it) {
         const int q = it * 64 + lane;
-        if (q < count) {
-          const double xq = s_x[wv][q];
-          double acc;
-          if (q < nA) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
-          else if (q < nAC) acc = wsum_region_c(xq, k, tc);
-          else acc = wsum_sweep_b<CH, TS>(xq, k, tb, top_b);
-          s_x[wv][q] = acc;
-        }
+        const double xq = s_x[wv][q];
+        double acc;
+        if (q < nA) acc = wsum_sweep_a<CH, TS>(xq, k, ta);
+        else if (q < nAC) acc = wsum_region_c(xq, k, tc);
+        else acc = wsum_sweep_b<CH, TS>(xq, k, tb, top_b);
+        s_x[wv][q] = acc;
       }
       wave_sync();
       // Non-temporal stores: the output is not read again by the kernel.
