@@ -42,10 +42,13 @@ def test_paper_distribution_all_rows():
     check(x, y, c, z, np.arange(x.size))
 
 
-@pytest.mark.parametrize("kmax", [0, 1, 5, 20, 32, 33, 36, 40])
+@pytest.mark.parametrize("kmax", [0, 1, 2, 3, 5, 12, 13, 20, 24, 32, 33, 36, 40])
 def test_orders(kmax):
     """Orders up to 32 with the paper's tables, 33..40 with the high-order
-    set; pair arguments up to 80 cross both sets' region boundaries."""
+    set; pair arguments up to 80 cross both sets' region boundaries.  Region
+    A's closed form reads its coefficients as kernel arguments up to order
+    12 and from LDS from 13 on, and the LDS Horner passes take two pairs per
+    chunk, so odd and even orders on both sides are included."""
     x, y, c = workloads.pair_workload(n=600, kmax=kmax, seed=10 + kmax, x_max=40.0)
     check(x, y, c, run(x, y, c), np.arange(0, 600, 3))
 
