@@ -101,9 +101,6 @@ __device__ __forceinline__ double pair_exp(double x, double eij) {
   return eij;
 }
 
-// sum_{l=0..K} c_l F_l(x) per region with the table set T: regions A and B
-// through their closed forms (PairAPoly, PairBPoly), region C by Horner in
-// 1/x; eij = e^-x_i e^-x_j (see pair_exp).
 // The closed forms' coefficient pairs live in LDS and are read through
 // pointers of this type.
 typedef __attribute__((address_space(3))) const wpair lds_wpair;
@@ -152,12 +149,16 @@ __device__ __forceinline__ wpair horner_pairs(double h, lds_wpair *&ab) {
 
 // Orders up to which region A's coefficients are read as kernel arguments
 // (SGPR addends of the Horner steps) rather than as LDS pairs: up to 12 they
-// fit in the scalar registers without spilling (106 SGPRs at order 12; 38
-// spilled at 16), and the paper's benchmark order 12 runs 2.8% faster than
-// with LDS pairs; above, LDS pairs (order 24: 190 ms against 230 ms with the
+// fit in the scalar registers of the pair loop (106 SGPRs at order 12, whose
+// 6 spilled ones are read back only outside the loop; at 16, 38 spilled
+// inside it), and the paper's benchmark order 12 runs 2.8% faster than with
+// LDS pairs; above, LDS pairs (order 24: 190 ms against 230 ms with the
 // spills, n = 2^18).
 constexpr int kPairSgprOrders = 12;
 
+// sum_{l=0..K} c_l F_l(x) per region with the table set T: regions A and B
+// through their closed forms (PairAPoly, PairBPoly), region C by Horner in
+// 1/x; eij = e^-x_i e^-x_j (see pair_exp).
 template <int K, class T>
 __device__ __forceinline__ double pair_weighted(double x, double eij, const PairAPoly &ap,
                                                 const PairWeights &dw, lds_wpair *&uv,
