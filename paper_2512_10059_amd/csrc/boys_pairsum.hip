@@ -6,8 +6,8 @@
 // accumulated inside the recurrence.  The work is VALU-bound (no per-pair
 // memory traffic).
 //
-// Divergence control: the arguments are first sorted (rocPRIM radix sort of
-// (x, index) pairs), so the 64 rows of a wave hold nearly equal x_i and, for
+// Divergence control: the arguments are first sorted (a bitonic sort of
+// (x, index) pairs, below), so the 64 rows of a wave hold nearly equal x_i and, for
 // a given j, x_i + x_j falls in one region for the whole wave except within
 // a sliver around the region boundaries.  Rows are evaluated in sorted order
 // and the results scattered back.  Each thread owns one row i; the j loop
@@ -23,8 +23,6 @@
 #include <mutex>
 #include <vector>
 #include <utility>
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "boys.h"
 #include "boys_common.hpp"
@@ -270,18 +268,114 @@ __global__ __launch_bounds__(kBlock) void pairsum_kernel(const double *__restric
   if (i < n) zs[i] = total;
 }
 
-__global__ void iota_kernel(int32_t *idx, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) idx[i] = int32_t(i);
+// ---------------------------------------------------------------------------
+// The sort that orders the arguments: a bitonic network over N = 2^p >= n
+// records (key, index), where key is the double's bit pattern mapped to an
+// unsigned integer of the same order (sign bit set: all bits flipped; else
+// the sign bit set) and index the argument's position.  Records compare by
+// key, then by index, so the order is total and the result is that of a
+// stable sort by x; the N - n padding records (all-ones key and index) sort
+// last.  The order only steers divergence: any permutation gives the same
+// sums, so correctness needs only that the first n indices be a permutation
+// of 0..n-1, which every compare-exchange network preserves.
+//
+// Stages with a partner distance j >= kSortSeg/2 run as one global kernel
+// each (one compare-exchange per thread); the stages below, and the whole
+// sort of each kSortSeg-record segment at the start, run in LDS.  At n = 2^19
+// that is 45 launches moving about 0.2 GB, against the pair kernel's 0.4 s.
+constexpr int kSortSeg = 2048;  // records per LDS segment (24 KB)
+
+__device__ __forceinline__ uint64_t order_key(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  return (b >> 63) ? ~b : (b | (uint64_t(1) << 63));
 }
 
-__global__ void gather_kernel(const double *__restrict__ y, const int32_t *__restrict__ idx,
+// (ka, ia) after (kb, ib) in the sort order.
+__device__ __forceinline__ bool rec_after(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+  return ka > kb || (ka == kb && ia > ib);
+}
+
+__global__ void sort_keys_kernel(const double *__restrict__ x, int64_t n, int64_t N,
+                                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  keys[i] = i < n ? order_key(x[i]) : ~uint64_t(0);
+  vals[i] = i < n ? uint32_t(i) : ~uint32_t(0);
+}
+
+// Stages (k, j) for k = kmin, 2 kmin, .., kmax and, within each, j from
+// min(k/2, jmax) down to 1, on each segment of seg records (seg a power of
+// two <= kSortSeg, j < seg).  Direction by the record's global position i:
+// ascending where (i & k) == 0.
+__global__ __launch_bounds__(kBlock) void sort_segment_kernel(uint64_t *__restrict__ keys,
+                                                              uint32_t *__restrict__ vals, int seg,
+                                                              int64_t kmin, int64_t kmax, int jmax) {
+  __shared__ uint64_t sk[kSortSeg];
+  __shared__ uint32_t sv[kSortSeg];
+  const int64_t base = int64_t(blockIdx.x) * seg;
+  for (int t = threadIdx.x; t < seg; t += kBlock) {
+    sk[t] = keys[base + t];
+    sv[t] = vals[base + t];
+  }
+  __syncthreads();
+  for (int64_t k = kmin; k <= kmax; k <<= 1) {
+    for (int j = int(k >> 1 < jmax ? k >> 1 : jmax); j > 0; j >>= 1) {
+      for (int p = threadIdx.x; p < seg / 2; p += kBlock) {
+        const int lo = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // bit j clear
+        const int hi = lo | j;
+        const bool up = ((base + lo) & k) == 0;
+        const uint64_t ka = sk[lo], kb = sk[hi];
+        const uint32_t ia = sv[lo], ib = sv[hi];
+        if (rec_after(ka, ia, kb, ib) == up) {
+          sk[lo] = kb;
+          sk[hi] = ka;
+          sv[lo] = ib;
+          sv[hi] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < seg; t += kBlock) {
+    keys[base + t] = sk[t];
+    vals[base + t] = sv[t];
+  }
+}
+
+// One stage (k, j), j >= kSortSeg / 2, over N records: thread p takes the
+// pair (lo, lo + j) with bit j of lo clear, p < N/2.
+__global__ __launch_bounds__(kBlock) void sort_stage_kernel(uint64_t *__restrict__ keys,
+                                                            uint32_t *__restrict__ vals, int64_t half,
+                                                            int64_t k, int64_t j) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= half) return;
+  const int64_t lo = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+  const int64_t hi = lo | j;
+  const bool up = (lo & k) == 0;
+  const uint64_t ka = keys[lo], kb = keys[hi];
+  const uint32_t ia = vals[lo], ib = vals[hi];
+  if (rec_after(ka, ia, kb, ib) == up) {
+    keys[lo] = kb;
+    keys[hi] = ka;
+    vals[lo] = ib;
+    vals[hi] = ia;
+  }
+}
+
+// The rows in sorted order: x and y permuted by the sorted indices (the
+// first n, all below n).
+__global__ void gather_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                              const uint32_t *__restrict__ idx, double *__restrict__ xs,
                               double *__restrict__ ys, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) ys[i] = y[idx[i]];
+  if (i < n) {
+    const uint32_t r = idx[i];
+    xs[i] = x[r];
+    ys[i] = y[r];
+  }
 }
 
-__global__ void scatter_kernel(const double *__restrict__ zs, const int32_t *__restrict__ idx,
+__global__ void scatter_kernel(const double *__restrict__ zs, const uint32_t *__restrict__ idx,
                                double *__restrict__ z, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) z[idx[i]] = zs[i];
@@ -312,7 +406,7 @@ constexpr auto make_high_table(std::index_sequence<I...>) {
 }
 constexpr auto kPairTableHigh = make_high_table(std::make_index_sequence<kHighKmax - kF64Kmax>{});
 
-// Per-device workspace: sorted keys, indices, permuted y and z, sort scratch.
+// Per-device workspace: sort records (keys, indices), permuted x, y and z.
 struct PairState {
   std::mutex mu;
   void *buf = nullptr;
@@ -410,20 +504,15 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
     }
   }
 
-  size_t sort_bytes = 0;
-  BOYS_TRY_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, static_cast<const double *>(nullptr),
-                                         static_cast<double *>(nullptr),
-                                         static_cast<const int32_t *>(nullptr),
-                                         static_cast<int32_t *>(nullptr), size_t(n), 0, 64,
-                                         stream));
-  const size_t un = size_t(n);
+  int64_t N = 1;  // records of the sort: the power of two >= n
+  while (N < n) N <<= 1;
+  const size_t un = size_t(n), uN = size_t(N);
   const size_t off_keys = 0;
-  const size_t off_idx_in = off_keys + align256(8 * un);
-  const size_t off_idx = off_idx_in + align256(4 * un);
-  const size_t off_ys = off_idx + align256(4 * un);
+  const size_t off_vals = off_keys + align256(8 * uN);
+  const size_t off_xs = off_vals + align256(4 * uN);
+  const size_t off_ys = off_xs + align256(8 * un);
   const size_t off_zs = off_ys + align256(8 * un);
-  const size_t off_tmp = off_zs + align256(8 * un);
-  size_t need = off_tmp + align256(sort_bytes);
+  size_t need = off_zs + align256(8 * un);
 
   PairState &s = g_pair[dev];
   std::lock_guard<std::mutex> lock(s.mu);
@@ -445,26 +534,45 @@ extern "C" int boys_pairsum_tol(const double *x, const double *y, int64_t n, con
     s.bytes = need;
   }
   char *base = static_cast<char *>(s.buf);
-  double *keys = reinterpret_cast<double *>(base + off_keys);
-  int32_t *idx_in = reinterpret_cast<int32_t *>(base + off_idx_in);
-  int32_t *idx = reinterpret_cast<int32_t *>(base + off_idx);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(base + off_keys);
+  uint32_t *vals = reinterpret_cast<uint32_t *>(base + off_vals);
+  double *xs = reinterpret_cast<double *>(base + off_xs);
   double *ys = reinterpret_cast<double *>(base + off_ys);
   double *zs = reinterpret_cast<double *>(base + off_zs);
-  void *tmp = base + off_tmp;
 
   const unsigned g = unsigned((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(iota_kernel, dim3(g), dim3(kBlock), 0, stream, idx_in, n);
+  hipLaunchKernelGGL(sort_keys_kernel, dim3(unsigned((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, x,
+                     n, N, keys, vals);
   BOYS_TRY_HIP(hipGetLastError());
-  BOYS_TRY_HIP(rocprim::radix_sort_pairs(tmp, sort_bytes, x, keys, idx_in, idx, un, 0, 64, stream));
-  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, y, idx, ys, n);
+  // Segments sorted in LDS (directions alternating with the global
+  // position), then each merge size k > seg: global stages while j >= seg,
+  // the rest in LDS.
+  const int seg = int(N < kSortSeg ? N : kSortSeg);
+  const unsigned nseg = unsigned(N / seg);
+  if (N > 1) {
+    hipLaunchKernelGGL(sort_segment_kernel, dim3(nseg), dim3(kBlock), 0, stream, keys, vals, seg, int64_t(2),
+                       int64_t(seg), seg);
+    BOYS_TRY_HIP(hipGetLastError());
+  }
+  const unsigned gh = unsigned((N / 2 + kBlock - 1) / kBlock);
+  for (int64_t k = int64_t(seg) << 1; k <= N; k <<= 1) {
+    for (int64_t j = k >> 1; j >= seg; j >>= 1) {
+      hipLaunchKernelGGL(sort_stage_kernel, dim3(gh), dim3(kBlock), 0, stream, keys, vals, N / 2, k, j);
+      BOYS_TRY_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(sort_segment_kernel, dim3(nseg), dim3(kBlock), 0, stream, keys, vals, seg, k, k,
+                       seg >> 1);
+    BOYS_TRY_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, stream, x, y, vals, xs, ys, n);
   BOYS_TRY_HIP(hipGetLastError());
   PairKernel kernel = kPairTable[kmax < kF64Kmax ? kmax : kF64Kmax];
   if (set == kSetHigh) kernel = kPairTableHigh[kmax - kF64Kmax - 1];
   else if (set == kSetScreen) kernel = kPairTableScreen[kmax];
   else if (table_variant() == BOYS_TABLES_PER_KMAX) kernel = kPairTablePerKmax[kmax];
   else if (table_variant() == BOYS_TABLES_CENTRE) kernel = kPairTableCentre[kmax];
-  hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, keys, ys, n, ap, dw, bp, zs);
+  hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), 0, stream, xs, ys, n, ap, dw, bp, zs);
   BOYS_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, idx, z, n);
+  hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(kBlock), 0, stream, zs, vals, z, n);
   return hip_status(hipGetLastError());
 }

@@ -157,3 +157,18 @@ def test_one_negative_operand_among_many():
     ok = np.flatnonzero(~nan_rows)
     rows = np.concatenate([ok[(ok >= 1664) & (ok < 1728)][:8], ok[::97]])
     check(x, y, c, z, rows)
+
+
+def test_sort_with_ties_past_one_segment():
+    """5000 arguments (8192 sort records: LDS segments of 2048 plus global
+    merge stages) drawn from 40 distinct values, so most keys tie: the
+    rows must match the oracle, and two calls must agree bit for bit (the
+    sort orders ties by position, so its permutation is fixed)."""
+    rng = np.random.default_rng(13)
+    vals = np.sort(rng.uniform(0.0, 20.0, 40))
+    x = rng.choice(vals, 5000)
+    y = rng.standard_normal(x.size)
+    c = rng.standard_normal(8)
+    z = run(x, y, c)
+    assert np.array_equal(z, run(x, y, c))
+    check(x, y, c, z, np.concatenate([np.arange(0, 5000, 97), [4999]]))
