@@ -140,7 +140,8 @@ __device__ __forceinline__ wpair horner_pairs(double h, lds_wpair *&ab) {
         Q = __builtin_fma(Q, h, cur[s].y);
       }
 #pragma unroll
-    for (int s = 0; s < C; ++s) cur[s] = nxt[s];
+    for (int s = 0; s < C; ++s)
+      if (l0 - C - s >= 0) cur[s] = nxt[s];  // the entries loaded above
   }
   return wpair{P, Q};
 }
