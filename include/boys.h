@@ -320,8 +320,9 @@ BOYS_API int boys_backward_tol(const double *x, const double *grad_f, int64_t n,
  * order), so its rounding is about (512 + n/512) ulps of sum_j |y_j w_ij|
  * on top of the method's 5e-14 sum_l |c_l| per term.  The arguments are
  * sorted on the device first (rows evaluated in sorted order, results
- * scattered back), which needs a per-device workspace of about 32 n bytes
- * plus sort scratch, allocated on first use and grown when n grows.
+ * scattered back), which needs a per-device workspace of 12 N + 24 n bytes,
+ * N the power of two at or above n (at most 48 n bytes), allocated on first
+ * use and grown when n grows.
  * Errors: BOYS_EINVAL for bad sizes, orders, null or overlapping pointers;
  * BOYS_ENOMEM if the workspace cannot grow; BOYS_ECAPTURE on a stream under
  * graph capture.
