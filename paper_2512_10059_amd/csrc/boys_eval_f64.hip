@@ -64,10 +64,17 @@ __global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
     const int64_t row0 = blk * (64 * WB) + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     double F[C];
+    // Waves evaluate at raised issue priority and store at the default: a
+    // wave still evaluating gets the SIMD ahead of waves in their store
+    // bursts, so it reaches its own stores sooner and the store stream stays
+    // fed.  Measured at kmax 32 on 2^26 arguments: 2.833 ms against 2.915
+    // ms without (raising the priority for the stores instead: 2.94 ms).
+    __builtin_amdgcn_s_setprio(3);
     boys_f64<K, T>(i < n ? x[i] : 0.0, F);
 #pragma unroll
     for (int l = 0; l < C; ++l) slice[lane * CP + l] = F[l];
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     const int64_t rows = n - row0 < 64 ? n - row0 : 64;
     if (contiguous && rows == 64) {
       // The wave's 64 rows are 64*C contiguous doubles = 32*C 16-byte units.
