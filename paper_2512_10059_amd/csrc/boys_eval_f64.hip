@@ -64,17 +64,21 @@ __global__ __launch_bounds__(64 * eval_waves(K)) void eval_f64_kernel(
     const int64_t row0 = blk * (64 * WB) + int64_t(wave) * 64;
     const int64_t i = row0 + lane;
     double F[C];
-    // Waves evaluate at raised issue priority and store at the default: a
-    // wave still evaluating gets the SIMD ahead of waves in their store
-    // bursts, so it reaches its own stores sooner and the store stream stays
-    // fed.  Measured at kmax 32 on 2^26 arguments: 2.833 ms against 2.915
-    // ms without (raising the priority for the stores instead: 2.94 ms).
-    __builtin_amdgcn_s_setprio(3);
+    // From kmax 8 on, where the store stream sets the time, waves evaluate
+    // at raised issue priority and store at the default: a wave still
+    // evaluating gets the SIMD ahead of waves in their store bursts, so it
+    // reaches its own stores sooner and the stream stays fed.  Measured on
+    // 2^26 arguments in alternating processes: kmax 32 2.825-2.827 ms
+    // against 2.901-2.909 ms without, kmax 16 1.583-1.591 against
+    // 1.691-1.693, kmax 8 0.925-0.928 against 0.963-0.978, kmax 12 and 24
+    // even; at kmax 0-4, bound by the evaluation, 1.5-2.5% slower, so not
+    // there.  Raising the priority for the stores instead was slower.
+    if constexpr (K >= 8) __builtin_amdgcn_s_setprio(3);
     boys_f64<K, T>(i < n ? x[i] : 0.0, F);
 #pragma unroll
     for (int l = 0; l < C; ++l) slice[lane * CP + l] = F[l];
     __syncthreads();
-    __builtin_amdgcn_s_setprio(0);
+    if constexpr (K >= 8) __builtin_amdgcn_s_setprio(0);
     const int64_t rows = n - row0 < 64 ? n - row0 : 64;
     if (contiguous && rows == 64) {
       // The wave's 64 rows are 64*C contiguous doubles = 32*C 16-byte units.
