@@ -172,3 +172,23 @@ def test_sort_with_ties_past_one_segment():
     z = run(x, y, c)
     assert np.array_equal(z, run(x, y, c))
     check(x, y, c, z, np.concatenate([np.arange(0, 5000, 97), [4999]]))
+
+
+def test_special_operands_in_the_sort():
+    """+0.0, -0.0 and +inf among 3000 ordinary operands: the sort's key
+    orders -0.0 below +0.0 and +inf above every finite value; the rows must
+    match the oracle (a pair with +inf has F_l = 0, so the +inf rows are 0
+    and the +inf columns add nothing).  A NaN operand then makes every row
+    NaN, since each row pairs with it."""
+    rng = np.random.default_rng(14)
+    x = np.concatenate([rng.uniform(0.0, 20.0, 3000), [0.0, -0.0, np.inf, 0.0, -0.0, np.inf]])
+    rng.shuffle(x)
+    y = rng.standard_normal(x.size)
+    c = rng.standard_normal(6)
+    z = run(x, y, c)
+    special = np.flatnonzero((x == 0.0) | np.isinf(x))
+    assert special.size == 6
+    check(x, y, c, z, np.concatenate([special, np.arange(0, x.size, 151)]))
+    assert np.all(z[np.isinf(x)] == 0.0)
+    x[17] = np.nan
+    assert np.isnan(run(x, y, c)).all()
