@@ -48,7 +48,10 @@ __global__ __launch_bounds__(kBlock) void eval_f32_kernel(const float *__restric
         const int u = lane + 64 * j;
         if (u < 16 * C) {
           f4 v;
-          if constexpr (CP == C && C % 4 == 0) {
+          if constexpr (CP == C) {
+            // Unpadded rows (odd C): the wave's rows are contiguous in LDS,
+            // so unit u is floats 4u..4u+3 of the slice, 16-byte aligned
+            // (slices start at multiples of 256 C bytes).
             v = reinterpret_cast<const f4 *>(slice)[u];
           } else {
 #pragma unroll
